@@ -1,0 +1,151 @@
+"""Pins of the oracle's w-svd (Alg. 2, Thm 2.5) and Moore-Penrose inverse (Def. 2.6, Remark 2.2)."""
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from pins import load_golden
+
+RM = load_golden("remark_2_2.json")
+
+
+def test_slice_svd_matches_gram_eigenvalues():
+    # A second library route: the squared singular values are the eigenvalues of M^T M.
+    rng = np.random.default_rng(2)
+    for shape in [(6, 4), (5, 5), (7, 3)]:
+        m = rng.standard_normal(shape)
+        u, s, v = orc.slice_svd(m)
+        ev = np.sort(np.linalg.eigvalsh(m.T @ m))[::-1]
+        np.testing.assert_allclose(s ** 2, ev, rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose((u * s) @ v.T, m, atol=1e-13)
+        for i in range(s.size):
+            assert u[np.argmax(np.abs(u[:, i])), i] > 0
+
+
+@pytest.mark.parametrize("p,L,n1,n2", [(16, 2, 8, 6), (8, 3, 5, 7), (4, 1, 6, 6)])
+def test_full_rank_reconstruction_and_orthogonality(p, L, n1, n2):
+    # Thm 2.5 with r = min(n1, n2): A = U *_w Sigma *_w V^T exactly, and U^T *_w U = I_r.
+    rng = np.random.default_rng(p + n1)
+    a = rng.standard_normal((p, n1, n2))
+    r = min(n1, n2)
+    uh, sh, vh, ak = orc.w_svd(a, L, r)
+    np.testing.assert_allclose(ak, a, atol=1e-12)
+    u, sig, v = orc.spatial_factors(uh, sh, vh, L)
+    usv = orc.w_product(orc.w_product(u, sig, L), orc.transpose(v), L)
+    np.testing.assert_allclose(usv, a, atol=1e-11)
+    eye = orc.identity(r, p, L)
+    np.testing.assert_allclose(orc.w_product(orc.transpose(u), u, L), eye, atol=1e-12)
+    np.testing.assert_allclose(orc.w_product(orc.transpose(v), v, L), eye, atol=1e-12)
+    assert np.all(np.diff(sh, axis=1) <= 0) and np.all(sh >= 0)
+
+
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_truncation_error_weighted_parseval(k):
+    # ||A - A_k||_F^2 = sum_c w_c sum_{i>k} sigma_{c,i}^2, with the weights of the
+    # closed-form inverse (2^L on s_L, 2^j / 4 on d_j).  The unweighted bound of
+    # Thm 2.5 does not hold for this non-orthogonal transform (Remark 2.1).
+    rng = np.random.default_rng(40 + k)
+    p, L = 16, 3
+    a = rng.standard_normal((p, 7, 6))
+    _, _, _, ak = orc.w_svd(a, L, k)
+    ah = orc.lift_fwd(a, L)
+    wts = orc.coefficient_weights(p, L)
+    tail = 0.0
+    for c in range(p):
+        s = np.linalg.svd(ah[c], compute_uv=False)
+        tail += wts[c] * np.sum(s[k:] ** 2)
+    err = np.sum((a - ak) ** 2)
+    assert abs(err - tail) <= 1e-11 * tail
+
+
+def test_theorem_2_5_unweighted_bound_counterexample():
+    # p = 2, L = 1, both slices I_2, r = 1: true error sqrt(2) exceeds the printed bound 1.
+    a = np.stack([np.eye(2), np.eye(2)])
+    _, _, _, ak = orc.w_svd(a, 1, 1)
+    err = np.linalg.norm((a - ak).ravel())
+    assert abs(err - np.sqrt(2.0)) < 1e-14
+
+
+def test_remark_2_2_values():
+    L = 1
+    a, b = RM["A"], RM["B"]
+    ah = orc.lift_fwd(a, L)
+    bh = orc.lift_fwd(b, L)
+    np.testing.assert_allclose(ah[0], RM["A_s"], atol=1e-15)
+    np.testing.assert_allclose(ah[1], RM["A_d"], atol=1e-15)
+    np.testing.assert_allclose(bh[0], RM["B_s"], atol=1e-15)
+    np.testing.assert_allclose(bh[1], RM["B_d"], atol=1e-15)
+    ab = orc.w_product(a, b, L)
+    abh = orc.lift_fwd(ab, L)
+    np.testing.assert_allclose(abh[0], RM["AB_s"], atol=1e-14)
+    np.testing.assert_allclose(abh[1], RM["AB_d"], atol=1e-14)
+    c = orc.w_pinv(ab, L)
+    ch = orc.lift_fwd(c, L)
+    np.testing.assert_allclose(ch[0], RM["C_s"], atol=1e-12)
+    np.testing.assert_allclose(ch[1], RM["C_d"], atol=1e-12)
+    np.testing.assert_allclose(c, RM["C"], atol=1e-12)
+    ap = orc.w_pinv(a, L)
+    bp = orc.w_pinv(b, L)
+    aph = orc.lift_fwd(ap, L)
+    bph = orc.lift_fwd(bp, L)
+    np.testing.assert_allclose(aph[0], RM["Apinv_s"], atol=1e-12)
+    np.testing.assert_allclose(aph[1], RM["Apinv_d"], atol=1e-12)
+    np.testing.assert_allclose(bph[0], RM["Bpinv_s"], atol=1e-12)
+    np.testing.assert_allclose(bph[1], RM["Bpinv_d"], atol=1e-12)
+    d = orc.w_product(bp, ap, L)
+    dh = orc.lift_fwd(d, L)
+    np.testing.assert_allclose(dh[0], RM["D_s"], atol=1e-12)
+    np.testing.assert_allclose(dh[1], RM["D_d"], atol=1e-12)
+    np.testing.assert_allclose(d, RM["D"], atol=1e-12)
+    assert not np.allclose(c, d)
+
+
+def _penrose(a, x, L):
+    axa = orc.w_product(orc.w_product(a, x, L), a, L)
+    xax = orc.w_product(orc.w_product(x, a, L), x, L)
+    ax = orc.w_product(a, x, L)
+    xa = orc.w_product(x, a, L)
+    return axa, xax, ax, xa
+
+
+@pytest.mark.parametrize("shape,L", [((8, 4, 6), 3), ((16, 5, 3), 2), ((4, 6, 6), 2)])
+def test_moore_penrose_conditions(shape, L):
+    # Def. 2.6: the four conditions hold for the per-slice construction (Thm 2.6).
+    rng = np.random.default_rng(sum(shape))
+    a = rng.standard_normal(shape)
+    a[:, :, -1] = a[:, :, 0]          # make slices rank deficient as well
+    x = orc.w_pinv(a, L)
+    axa, xax, ax, xa = _penrose(a, x, L)
+    np.testing.assert_allclose(axa, a, atol=1e-11)
+    np.testing.assert_allclose(xax, x, atol=1e-11)
+    np.testing.assert_allclose(orc.transpose(ax), ax, atol=1e-11)
+    np.testing.assert_allclose(orc.transpose(xa), xa, atol=1e-11)
+
+
+def test_moore_penrose_properties():
+    # Lemma 2.4 items 1-4.
+    rng = np.random.default_rng(77)
+    p, L = 8, 2
+    a = rng.standard_normal((p, 4, 6))
+    ap = orc.w_pinv(a, L)
+    np.testing.assert_allclose(orc.w_pinv(ap, L), a, atol=1e-10)
+    np.testing.assert_allclose(orc.w_pinv(orc.transpose(a), L), orc.transpose(ap), atol=1e-10)
+    aat = orc.w_product(a, orc.transpose(a), L)
+    np.testing.assert_allclose(orc.w_pinv(aat, L),
+                               orc.w_product(orc.w_pinv(orc.transpose(a), L), ap, L), atol=1e-10)
+    np.testing.assert_allclose(ap, orc.w_product(orc.transpose(a), orc.w_pinv(aat, L), L), atol=1e-10)
+
+
+def test_w_svd_rejects_bad_rank():
+    with pytest.raises(ValueError):
+        orc.w_svd(np.zeros((2, 3, 3)), 1, 4)
+    with pytest.raises(ValueError):
+        orc.w_svd(np.zeros((2, 3, 3)), 1, 0)
+
+
+def test_psnr_definition():
+    x = np.zeros((2, 3, 4))
+    y = x.copy()
+    y[0, 0, 0] = 0.1
+    # N = 24 samples, squared error 0.01 -> 10 log10(24 / 0.01)
+    assert abs(orc.psnr(x, y) - 10 * np.log10(2400.0)) < 1e-12
