@@ -1,0 +1,290 @@
+#!/usr/bin/env python3
+"""Benchmark of the w-product hot path on one MI355X.
+
+One step = one pass of the whole hot path over one batch of synthetic input:
+  * w-product forward + backward of A, B in R^{512x512x256} (N(0,1)), L = 4,
+    with the split-precision (bf16x3) face-products: forward lifting of A and B
+    with the hi/lo epilogue, the face-product, the inverse lifting, then
+    W^{-T} of the cotangent, the two transposed face-products and two W^T
+    passes (9 kernels);
+  * w-svd, k = 20, L = 3, of a 256x256x192 hyperspectral-like tensor
+    (lifting, Jacobi, rank-k rebuild, inverse lifting, FP64 orthogonality check).
+`value` is the effective w-product forward+backward rate, 3 * 2*n1*n2*n3*p
+flops divided by the w-product part of the step (HIP events on the stream
+the kernels run on).  FP32 and plain BF16 forward+backward are timed beside it
+outside the timed steps.  Prints one JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+P, N1, N2, N3, LEV = 256, 512, 512, 512, 4
+SVD_P, SVD_N, SVD_L, SVD_K = 192, 256, 3, 20
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFS = 2500.0          # dense BF16 MFMA
+FP32_PEAK_TFS = 157.3
+FP64_VALU_PEAK_TFS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle timing leg (used by profiler runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+class Marks:
+    """Records one event after each library call of a step, on the current stream."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.rows = []  # per step: list of (name, start_event, end_event)
+        self.cur = None
+        self.last = None
+
+    def begin(self):
+        ev = self.torch.cuda.Event(enable_timing=True)
+        ev.record()
+        self.cur = []
+        self.last = ev
+
+    def __call__(self, name):
+        ev = self.torch.cuda.Event(enable_timing=True)
+        ev.record()
+        self.cur.append((name, self.last, ev))
+        self.last = ev
+
+    def end(self):
+        self.rows.append(self.cur)
+
+    def per_kernel_ms(self):
+        """Mean duration of each named call over all recorded steps (ms, summed per step)."""
+        tot = {}
+        cnt = {}
+        for row in self.rows:
+            seen = {}
+            for name, a, b in row:
+                seen[name] = seen.get(name, 0.0) + a.elapsed_time(b)
+                cnt[name] = cnt.get(name, 0) + 1
+            for k, v in seen.items():
+                tot[k] = tot.get(k, 0.0) + v
+        n = len(self.rows)
+        return {k: v / n for k, v in tot.items()}, {k: cnt[k] // n for k in cnt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus %d is not supported "
+                          "(the w-product shards over whole 2^L-slice blocks with no exchange, "
+                          "see the design notes)" % args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_2601_08228_amd as wp
+    from paper_2601_08228_amd import synth, _lib
+    from paper_2601_08228_amd.autograd import forward_kernels, backward_kernels
+
+    _lib.load()  # fail loudly if the HIP library is missing
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    a = synth.normal_device((P, N1, N2), 21, dev)
+    b = synth.normal_device((P, N2, N3), 22, dev)
+    g = synth.normal_device((P, N1, N3), 102, dev)
+    x_hsi = torch.tensor(synth.hsi_like(SVD_N, SVD_N, SVD_P, seed=3), dtype=torch.float32,
+                         device=dev)
+    svd_ws = torch.empty(wp.w_svd_workspace(SVD_N, SVD_N, SVD_P, SVD_L, SVD_K), dtype=torch.uint8,
+                         device=dev)
+
+    marks = Marks(torch)
+
+    def wprod_step(gemm, mark):
+        c, saved = forward_kernels(a, b, LEV, gemm, mark)
+        da, db = backward_kernels(saved, g, LEV, gemm, mark=mark)
+        return c, da, db
+
+    def step():
+        marks.begin()
+        out = wprod_step("bf16x3", marks)
+        res = wp.w_svd(x_hsi, SVD_L, SVD_K, workspace=svd_ws)
+        marks("w_svd")
+        marks.end()
+        return out, res
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    marks.rows.clear()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out, res = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    kern_ms, kern_cnt = marks.per_kernel_ms()
+    wprod_ms = sum(v for k, v in kern_ms.items() if k != "w_svd")
+    flops = 2.0 * N1 * N2 * N3 * P
+    value = 3.0 * flops / (wprod_ms * 1e-3) / 1e12
+    info = res.info.cpu().numpy()
+    orth = res.orth_err.cpu().numpy()
+    c_x3, da_x3, db_x3 = out
+
+    # ---- comparisons outside the timed steps: FP32 and plain BF16 fwd+bwd ----
+    def time_mode(gemm, reps=5):
+        wprod_step(gemm, lambda n: None)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            o = wprod_step(gemm, lambda n: None)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, o
+
+    fp32_ms, (c32, da32, db32) = time_mode("native")
+    bf16_ms, (c16, _, _) = time_mode("bf16")
+
+    def rel(x, y):
+        return float(torch.linalg.vector_norm((x - y).double()) / torch.linalg.vector_norm(y.double()))
+
+    rel_x3_fp32 = max(rel(c_x3, c32), rel(da_x3, da32), rel(db_x3, db32))
+    rel_bf16_fp32 = rel(c16, c32)
+
+    if args.copy_calibration:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    # ---- roofline of every kernel of the step --------------------------------
+    tensor_b = P * N1 * N2 * 4            # one 512x512x256 FP32 tensor
+    bytes_per = {
+        "lift_fwd_split": tensor_b + tensor_b,          # read FP32, write bf16 hi + lo
+        "lift_inv": 2 * tensor_b,
+        "lift_inv_adj_split": 2 * tensor_b,
+        "lift_fwd_adj": 2 * tensor_b,
+    }
+    rows = {}
+    for name, ms in kern_ms.items():
+        launches = kern_cnt[name]
+        per_launch_ms = ms / launches
+        if name in bytes_per:
+            ach = bytes_per[name] / (per_launch_ms * 1e-3) / 1e9
+            rows[name] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                          "launches_per_step": launches, "ms_per_launch": round(per_launch_ms, 4),
+                          "algorithmic_bytes_per_launch": bytes_per[name]}
+        elif name.startswith("face"):
+            ach = flops / (per_launch_ms * 1e-3) / 1e12
+            peak = BF16_PEAK_TFS / 3.0  # three BF16 products per effective product
+            rows[name] = {"bound": "mfma", "achieved": round(ach, 2), "peak": round(peak, 1),
+                          "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+                          "launches_per_step": launches, "ms_per_launch": round(per_launch_ms, 4),
+                          "algorithmic_flops_per_launch": flops}
+    # dominant kernel of the w-product part (the w-svd call is several kernels)
+    dom_name = max(rows, key=lambda k: kern_ms[k])
+    roof = dict(rows[dom_name])
+    roof["kernel"] = dom_name
+    roof["traffic"] = None
+
+    # ---- CPU baseline: the oracle on a bounded sample of the same workload ----
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(torch, a, b, g, c_x3, da_x3)
+
+    line = {
+        "metric": "w-product fwd+bwd effective TFLOP/s (bf16x3 face-products, 512x512x256, L=4)",
+        "value": round(value, 2),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3",
+        "data": "synthetic",
+        "config": {
+            "workload": "w-product fwd+bwd, A,B 512x512x256 N(0,1), L=4, bf16x3 "
+                        "+ w-svd k=20 of a 256x256x192 hyperspectral-like tensor, L=3",
+            "w_product": {"n1": N1, "n2": N2, "n3": N3, "p": P, "L": LEV, "gemm": "bf16x3"},
+            "w_svd": {"n1": SVD_N, "n2": SVD_N, "p": SVD_P, "L": SVD_L, "k": SVD_K},
+        },
+        "parts_ms": {"w_product_fwd_bwd": round(wprod_ms, 4), "w_svd": round(kern_ms["w_svd"], 4)},
+        "kernel_ms_per_step": {k: round(v, 4) for k, v in kern_ms.items()},
+        "fp32_fwd_bwd_ms": round(fp32_ms, 4),
+        "bf16_fwd_bwd_ms": round(bf16_ms, 4),
+        "bf16x3_fwd_bwd_ms": round(wprod_ms, 4),
+        "bf16x3_speedup_vs_fp32": round(fp32_ms / wprod_ms, 3),
+        "rel_diff_bf16x3_vs_fp32": rel_x3_fp32,
+        "rel_diff_bf16_vs_fp32": rel_bf16_fp32,
+        "w_svd_sweeps": [int(info.min()), int(info.max())],
+        "w_svd_orth_err": [float(orth[0]), float(orth[1])],
+        "roofline": roof,
+        "roofline_kernels": rows,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(torch, a, b, g, c_gpu, da_gpu):
+    """Oracle w-product fwd+bwd on rows [0, 64) of A (1/8 of the work), timed on host cores."""
+    import oracle
+    rows = 64
+    a_s = a[:, :rows, :].double().cpu().numpy()
+    b_h = b.double().cpu().numpy()
+    g_s = g[:, :rows, :].double().cpu().numpy()
+    t0 = time.perf_counter()
+    c_ref = oracle.w_product(a_s, b_h, LEV)
+    da_ref, _db_part = oracle.w_product_vjp(a_s, b_h, g_s, LEV)
+    t1 = time.perf_counter()
+    sample_flops = 3.0 * 2.0 * rows * N2 * N3 * P
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # threadpoolctl missing: report the visible cores
+        threads = os.cpu_count()
+
+    def rel(x, ref):
+        return float(np.linalg.norm((x - ref).ravel()) / np.linalg.norm(ref.ravel()))
+
+    return {
+        "value": round(sample_flops / (t1 - t0) / 1e12, 6),
+        "unit": "TFLOP/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": "FP64 NumPy oracle, w-product fwd+bwd of rows 0..63 of A (64x512 by 512x512, "
+                  "256 slices, L=4): 1/8 of the step's w-product work; %.1f s" % (t1 - t0),
+        "seconds": round(t1 - t0, 3),
+        "rel_err_gpu_bf16x3_vs_oracle": {
+            "C_rows0_63": rel(c_gpu[:, :rows, :].double().cpu().numpy(), c_ref),
+            "dA_rows0_63": rel(da_gpu[:, :rows, :].double().cpu().numpy(), da_ref),
+        },
+    }
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,165 @@
+/*
+ * wprod.h - C ABI of the MI355X (gfx950) w-product library, libwprod.so.
+ *
+ * The w-product of Panchal & Behera (arXiv 2601.08228) multiplies third-order
+ * tensors through a lazy lifting wavelet transform along mode 3 (Sec. II-A,
+ * Eq. (1)), slice-wise matrix products of the coefficients (the face-product
+ * of Def. 2.1) and the inverse transform (Alg. 1); the w-svd replaces the
+ * products by per-slice truncated SVDs (Alg. 2, Thm 2.5).
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * Memory.  Every tensor pointer is a DEVICE pointer on the calling thread's
+ *   current HIP device, allocated and owned by the caller.  The library keeps
+ *   no global state and allocates no device memory; where scratch is needed
+ *   the caller passes a workspace whose size a *_workspace() query returns.
+ * Layout.  A tensor X in R^{n1 x n2 x p} is p contiguous row-major n1 x n2
+ *   frontal slices: X[i, j, k] (0-based) lives at element k*n1*n2 + i*n2 + j
+ *   (a C-contiguous array of shape (p, n1, n2)).  A coefficient tensor has
+ *   the same shape with its slices in the order of Eq. (1): s_L, d_L,
+ *   d_{L-1}, ..., d_1, where with m = p / 2^L, s_L occupies slices [0, m) and
+ *   d_j occupies slices [p / 2^j, p / 2^(j-1)).
+ * Transform.  The lazy lifting of Sec. II-A (P_j = I, U_j = I/2): each level
+ *   splits the smooth sequence into pairs (first, second) = (slice 2q, slice
+ *   2q+1), d = first - second, s = second + d/2.  p must be a positive
+ *   multiple of 2^L; 0 <= L <= 10 (L = 0 is the identity transform).
+ * Types.  WP_F64 (double) or WP_F32 (float) elements.  Split-precision
+ *   coefficients are two arrays of bfloat16 bit patterns (uint16_t) of the
+ *   same shape: hi = bf16_rne(x), lo = bf16_rne(x - hi).
+ * Streams.  `stream` is a hipStream_t (NULL = the null stream).  Every entry
+ *   point only enqueues work on it and returns without synchronising; results
+ *   are ready when the stream reaches that point.
+ * Errors.  Arguments are validated before any HIP call; on an error nothing is
+ *   launched, no output is touched, and a negative wp_status is returned.
+ *   NaN/Inf inputs are not screened and propagate.  Outputs must not overlap
+ *   inputs or each other (WP_EALIAS).  Sizes: every dimension >= 1 and each
+ *   tensor below 2^40 elements.
+ */
+#ifndef WPROD_H
+#define WPROD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int wp_status;
+#define WP_OK           0
+#define WP_EINVAL      -1   /* bad size, level, rank or flag                    */
+#define WP_ENULL       -2   /* required pointer is NULL                          */
+#define WP_EALIAS      -3   /* an output overlaps an input or another output     */
+#define WP_EDTYPE      -4   /* unknown dtype, or GEMM mode not valid for dtype   */
+#define WP_EWORKSPACE  -5   /* workspace smaller than the *_workspace() query    */
+#define WP_ELAUNCH     -6   /* a HIP launch or runtime call failed               */
+#define WP_ENOCONV     -7   /* reported by callers when a Jacobi slice did not converge */
+
+#define WP_F64 0
+#define WP_F32 1
+
+#define WP_GEMM_NATIVE 0    /* F64 data on FP64 MFMA, F32 data on FP32 MFMA      */
+#define WP_GEMM_BF16   1    /* F32 data, products of bf16 hi parts, FP32 accumulation */
+#define WP_GEMM_BF16X3 2    /* F32 data, hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 accumulation */
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char* w_status_string(wp_status s);
+
+/* Library ABI version (major*10000 + minor*100 + patch). */
+int w_version(void);
+
+/* ---- Transforms (Sec. II-A) -------------------------------------------------
+ * In: x or coefficients, (p, n1, n2) of `dtype`.  Out: same shape and dtype.
+ */
+
+/* Forward lifting W_[L] along mode 3, Eq. (1) / Alg. 1 forward steps:
+ * x (spatial) -> xhat (coefficients, Eq. (1) order). */
+wp_status w_transform(const void* x, void* xhat, int64_t n1, int64_t n2, int64_t p,
+                      int L, int dtype, void* stream);
+
+/* Inverse lifting W_[L]^{-1}, Eq. (3) / Alg. 1 inverse steps: xhat -> x. */
+wp_status w_itransform(const void* xhat, void* x, int64_t n1, int64_t n2, int64_t p,
+                       int L, int dtype, void* stream);
+
+/* Transpose W_[L]^T (adjoint of w_transform, derived from its level steps):
+ * coefficient-space g -> spatial out.  Used by the reverse-mode derivative. */
+wp_status w_transform_adj(const void* g, void* out, int64_t n1, int64_t n2, int64_t p,
+                          int L, int dtype, void* stream);
+
+/* Transpose of the inverse, W_[L]^{-T}: spatial g -> coefficient-space out. */
+wp_status w_itransform_adj(const void* g, void* out, int64_t n1, int64_t n2, int64_t p,
+                           int L, int dtype, void* stream);
+
+/* w_transform of float data with a split-precision epilogue: writes
+ * hi = bf16_rne(xhat) and lo = bf16_rne(xhat - hi) (lo may be NULL: hi only). */
+wp_status w_transform_split(const float* x, uint16_t* xhat_hi, uint16_t* xhat_lo,
+                            int64_t n1, int64_t n2, int64_t p, int L, void* stream);
+
+/* w_itransform_adj of float data with the same split-precision epilogue. */
+wp_status w_itransform_adj_split(const float* g, uint16_t* out_hi, uint16_t* out_lo,
+                                 int64_t n1, int64_t n2, int64_t p, int L, void* stream);
+
+/* ---- Face-product (Def. 2.1, Alg. 1 middle part) ----------------------------
+ * Ch[k] = op(Ah[k]) * op(Bh[k]) for k = 0..p-1, with op(X) = X or X^T per
+ * slice (Def. 2.2).  op(Ah[k]) is n1 x n2, op(Bh[k]) is n2 x n3, Ch is
+ * (p, n1, n3).  Stored shapes: Ah (p, n1, n2), or (p, n2, n1) if trans_a;
+ * Bh (p, n2, n3), or (p, n3, n2) if trans_b.  Transposing before or after the
+ * transform is the same (Thm 2.1), so the flags apply to spatial operands too.
+ */
+
+/* Native precision: WP_F64 on FP64 MFMA, WP_F32 on FP32 MFMA (FP32 accumulation). */
+wp_status w_face_product(const void* ah, const void* bh, void* ch,
+                         int64_t n1, int64_t n2, int64_t n3, int64_t p,
+                         int trans_a, int trans_b, int dtype, void* stream);
+
+/* Split precision on BF16 MFMA with FP32 accumulation.  gemm = WP_GEMM_BF16
+ * uses a_hi*b_hi only (a_lo, b_lo may be NULL); WP_GEMM_BF16X3 adds a_hi*b_lo
+ * + a_lo*b_hi (all four arrays required).  Output ch is float. */
+wp_status w_face_product_split(const uint16_t* a_hi, const uint16_t* a_lo,
+                               const uint16_t* b_hi, const uint16_t* b_lo, float* ch,
+                               int64_t n1, int64_t n2, int64_t n3, int64_t p,
+                               int trans_a, int trans_b, int gemm, void* stream);
+
+/* ---- w-product (Def. 2.1, Alg. 1) ------------------------------------------
+ * C = op(A) *_w op(B) = W^{-1}( W(op A) Delta W(op B) ); C is (p, n1, n3).
+ * gemm selects the face-product arithmetic (WP_GEMM_*; BF16 modes need
+ * WP_F32).  ws must hold w_product_workspace(...) bytes (256-byte aligned
+ * pointer recommended; any alignment is accepted).
+ */
+wp_status w_product(const void* a, const void* b, void* c,
+                    int64_t n1, int64_t n2, int64_t n3, int64_t p, int L,
+                    int trans_a, int trans_b, int dtype, int gemm,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for w_product (0 on invalid arguments). */
+size_t w_product_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int L,
+                           int dtype, int gemm);
+
+/* ---- w-svd (Alg. 2, Thm 2.5) ------------------------------------------------
+ * Truncated SVD of every coefficient slice of W(A), A (p, n1, n2), by one-sided
+ * Jacobi with FP64 rotation parameters (dot products and angles in FP64; data
+ * stays in `dtype`).  Outputs (wavelet-domain factors, Thm 2.5):
+ *   uhat (p, n1, k), shat (p, k) descending and >= 0, vhat (p, n2, k),
+ *   ak (p, n1, n2) = W^{-1}(uhat_k diag(shat_k) vhat_k^T), or NULL to skip.
+ * Signs: in each column of uhat the entry of largest magnitude is positive
+ * (lowest row wins ties); the matching vhat column is flipped with it.
+ * info (p int32, device): sweeps used by slice k if it converged, minus the
+ *   sweeps run if it did not (max_sweeps reached, or a non-finite value met).
+ * orth_err (2 doubles, device, or NULL): max over slices of
+ *   max|uhat^T uhat - I| and of max|vhat^T vhat - I|, evaluated in FP64.
+ * 1 <= k <= min(n1, n2); max_sweeps >= 1 (<= 0 selects 30 for F64, 20 for F32);
+ * n1, n2 <= 1024.  ws must hold w_svd_workspace(...) bytes.
+ */
+wp_status w_svd(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k,
+                void* uhat, void* shat, void* vhat, void* ak, int max_sweeps,
+                int32_t* info, double* orth_err, int dtype,
+                void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for w_svd (0 on invalid arguments). */
+size_t w_svd_workspace(int64_t n1, int64_t n2, int64_t p, int L, int k, int dtype);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WPROD_H */

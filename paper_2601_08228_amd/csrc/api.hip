@@ -1,0 +1,328 @@
+// extern "C" entry points of libwprod.so: argument validation (before any HIP
+// call), workspace carving and kernel dispatch.  See include/wprod.h for the
+// contract of each call.
+
+#include "wprod.h"
+#include "wp_internal.h"
+
+namespace {
+
+using wp::LiftKind;
+
+constexpr int64_t kMaxElems = int64_t(1) << 40;
+constexpr size_t kAlign = 256;
+
+struct Range {
+  const char* lo;
+  const char* hi;
+};
+
+inline Range range_of(const void* p, int64_t elems, size_t esize) {
+  const char* c = static_cast<const char*>(p);
+  return Range{c, c + size_t(elems) * esize};
+}
+
+inline bool overlap(const Range& a, const Range& b) {
+  return a.lo != nullptr && b.lo != nullptr && a.lo < b.hi && b.lo < a.hi;
+}
+
+inline size_t dtype_size(int dtype) { return dtype == WP_F64 ? 8 : 4; }
+
+inline bool valid_dtype(int dtype) { return dtype == WP_F64 || dtype == WP_F32; }
+
+// Product of positive sizes with an overflow guard; -1 if too large.
+inline int64_t checked_mul(int64_t a, int64_t b) {
+  if (a <= 0 || b <= 0) return -1;
+  if (a > kMaxElems / b) return -1;
+  return a * b;
+}
+
+inline wp_status check_tensor(int64_t n1, int64_t n2, int64_t p, int L, int64_t* elems) {
+  if (n1 < 1 || n2 < 1 || p < 1) return WP_EINVAL;
+  if (L < 0 || L > wp::kMaxLevels) return WP_EINVAL;
+  if (p % (int64_t(1) << L) != 0) return WP_EINVAL;
+  const int64_t e = checked_mul(checked_mul(n1, n2), p);
+  if (e < 0) return WP_EINVAL;
+  if (n1 > INT32_MAX || n2 > INT32_MAX) return WP_EINVAL;
+  *elems = e;
+  return WP_OK;
+}
+
+inline wp_status from_hip(hipError_t e) { return e == hipSuccess ? WP_OK : WP_ELAUNCH; }
+
+wp_status run_lift(LiftKind kind, const void* in, void* out, int64_t n1, int64_t n2, int64_t p,
+                   int L, int dtype, void* stream) {
+  if (!valid_dtype(dtype)) return WP_EDTYPE;
+  int64_t elems = 0;
+  wp_status st = check_tensor(n1, n2, p, L, &elems);
+  if (st != WP_OK) return st;
+  if (in == nullptr || out == nullptr) return WP_ENULL;
+  const size_t es = dtype_size(dtype);
+  if (overlap(range_of(in, elems, es), range_of(out, elems, es))) return WP_EALIAS;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dtype == WP_F64)
+    return from_hip(wp::launch_lift_f64(kind, static_cast<const double*>(in),
+                                        static_cast<double*>(out), n1 * n2, p, L, s));
+  return from_hip(wp::launch_lift_f32(kind, static_cast<const float*>(in), static_cast<float*>(out),
+                                      n1 * n2, p, L, s));
+}
+
+wp_status run_lift_split(LiftKind kind, const float* in, uint16_t* hi, uint16_t* lo, int64_t n1,
+                         int64_t n2, int64_t p, int L, void* stream) {
+  int64_t elems = 0;
+  wp_status st = check_tensor(n1, n2, p, L, &elems);
+  if (st != WP_OK) return st;
+  if (in == nullptr || hi == nullptr) return WP_ENULL;
+  const Range rin = range_of(in, elems, 4);
+  const Range rhi = range_of(hi, elems, 2);
+  const Range rlo = range_of(lo, elems, 2);
+  if (overlap(rin, rhi) || overlap(rin, rlo) || overlap(rhi, rlo)) return WP_EALIAS;
+  return from_hip(wp::launch_lift_f32_split(kind, in, hi, lo, n1 * n2, p, L,
+                                            static_cast<hipStream_t>(stream)));
+}
+
+// Sizes of the three face-product operands, in elements.
+struct FaceShapes {
+  int64_t a, b, c;
+};
+
+inline wp_status check_face(int64_t n1, int64_t n2, int64_t n3, int64_t p, int ta, int tb,
+                            FaceShapes* fs) {
+  if (n1 < 1 || n2 < 1 || n3 < 1 || p < 1) return WP_EINVAL;
+  if ((ta != 0 && ta != 1) || (tb != 0 && tb != 1)) return WP_EINVAL;
+  if (n1 > INT32_MAX || n2 > INT32_MAX || n3 > INT32_MAX) return WP_EINVAL;
+  fs->a = checked_mul(checked_mul(n1, n2), p);
+  fs->b = checked_mul(checked_mul(n2, n3), p);
+  fs->c = checked_mul(checked_mul(n1, n3), p);
+  if (fs->a < 0 || fs->b < 0 || fs->c < 0) return WP_EINVAL;
+  return WP_OK;
+}
+
+struct ProductPlan {
+  size_t ah, ah_lo, bh, bh_lo, ch, total;  // byte offsets into the aligned workspace
+};
+
+// Workspace layout of w_product: transformed A, transformed B (split planes
+// for the BF16 modes), transformed C; each region 256-byte aligned, plus
+// 256 bytes of slack so that any caller alignment works.
+inline ProductPlan plan_product(const FaceShapes& fs, int dtype, int gemm) {
+  ProductPlan pl{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = wp::align_up(off + bytes, kAlign);
+    return at;
+  };
+  if (gemm == WP_GEMM_NATIVE) {
+    const size_t es = dtype_size(dtype);
+    pl.ah = take(size_t(fs.a) * es);
+    pl.bh = take(size_t(fs.b) * es);
+    pl.ch = take(size_t(fs.c) * es);
+  } else {
+    pl.ah = take(size_t(fs.a) * 2);
+    pl.ah_lo = gemm == WP_GEMM_BF16X3 ? take(size_t(fs.a) * 2) : 0;
+    pl.bh = take(size_t(fs.b) * 2);
+    pl.bh_lo = gemm == WP_GEMM_BF16X3 ? take(size_t(fs.b) * 2) : 0;
+    pl.ch = take(size_t(fs.c) * 4);
+  }
+  pl.total = off + kAlign;
+  return pl;
+}
+
+inline wp_status check_modes(int dtype, int gemm) {
+  if (!valid_dtype(dtype)) return WP_EDTYPE;
+  if (gemm != WP_GEMM_NATIVE && gemm != WP_GEMM_BF16 && gemm != WP_GEMM_BF16X3) return WP_EDTYPE;
+  if (gemm != WP_GEMM_NATIVE && dtype != WP_F32) return WP_EDTYPE;
+  return WP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* w_status_string(wp_status s) {
+  switch (s) {
+    case WP_OK: return "WP_OK";
+    case WP_EINVAL: return "WP_EINVAL: invalid size, level, rank or flag";
+    case WP_ENULL: return "WP_ENULL: required pointer is NULL";
+    case WP_EALIAS: return "WP_EALIAS: an output overlaps an input or another output";
+    case WP_EDTYPE: return "WP_EDTYPE: unknown dtype or GEMM mode not valid for the dtype";
+    case WP_EWORKSPACE: return "WP_EWORKSPACE: workspace too small";
+    case WP_ELAUNCH: return "WP_ELAUNCH: HIP launch or runtime call failed";
+    case WP_ENOCONV: return "WP_ENOCONV: a Jacobi slice did not converge";
+  }
+  return "unknown wp_status";
+}
+
+int w_version(void) { return 100; }
+
+wp_status w_transform(const void* x, void* xhat, int64_t n1, int64_t n2, int64_t p, int L,
+                      int dtype, void* stream) {
+  return run_lift(LiftKind::kForward, x, xhat, n1, n2, p, L, dtype, stream);
+}
+
+wp_status w_itransform(const void* xhat, void* x, int64_t n1, int64_t n2, int64_t p, int L,
+                       int dtype, void* stream) {
+  return run_lift(LiftKind::kInverse, xhat, x, n1, n2, p, L, dtype, stream);
+}
+
+wp_status w_transform_adj(const void* g, void* out, int64_t n1, int64_t n2, int64_t p, int L,
+                          int dtype, void* stream) {
+  return run_lift(LiftKind::kForwardAdj, g, out, n1, n2, p, L, dtype, stream);
+}
+
+wp_status w_itransform_adj(const void* g, void* out, int64_t n1, int64_t n2, int64_t p, int L,
+                           int dtype, void* stream) {
+  return run_lift(LiftKind::kInverseAdj, g, out, n1, n2, p, L, dtype, stream);
+}
+
+wp_status w_transform_split(const float* x, uint16_t* xhat_hi, uint16_t* xhat_lo, int64_t n1,
+                            int64_t n2, int64_t p, int L, void* stream) {
+  return run_lift_split(LiftKind::kForward, x, xhat_hi, xhat_lo, n1, n2, p, L, stream);
+}
+
+wp_status w_itransform_adj_split(const float* g, uint16_t* out_hi, uint16_t* out_lo, int64_t n1,
+                                 int64_t n2, int64_t p, int L, void* stream) {
+  return run_lift_split(LiftKind::kInverseAdj, g, out_hi, out_lo, n1, n2, p, L, stream);
+}
+
+wp_status w_face_product(const void* ah, const void* bh, void* ch, int64_t n1, int64_t n2,
+                         int64_t n3, int64_t p, int trans_a, int trans_b, int dtype,
+                         void* stream) {
+  if (!valid_dtype(dtype)) return WP_EDTYPE;
+  FaceShapes fs{};
+  wp_status st = check_face(n1, n2, n3, p, trans_a, trans_b, &fs);
+  if (st != WP_OK) return st;
+  if (ah == nullptr || bh == nullptr || ch == nullptr) return WP_ENULL;
+  const size_t es = dtype_size(dtype);
+  const Range rc = range_of(ch, fs.c, es);
+  if (overlap(rc, range_of(ah, fs.a, es)) || overlap(rc, range_of(bh, fs.b, es))) return WP_EALIAS;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dtype == WP_F64)
+    return from_hip(wp::launch_face_f64(static_cast<const double*>(ah), static_cast<const double*>(bh),
+                                        static_cast<double*>(ch), n1, n2, n3, p, trans_a != 0,
+                                        trans_b != 0, s));
+  return from_hip(wp::launch_face_f32(static_cast<const float*>(ah), static_cast<const float*>(bh),
+                                      static_cast<float*>(ch), n1, n2, n3, p, trans_a != 0,
+                                      trans_b != 0, s));
+}
+
+wp_status w_face_product_split(const uint16_t* a_hi, const uint16_t* a_lo, const uint16_t* b_hi,
+                               const uint16_t* b_lo, float* ch, int64_t n1, int64_t n2, int64_t n3,
+                               int64_t p, int trans_a, int trans_b, int gemm, void* stream) {
+  if (gemm != WP_GEMM_BF16 && gemm != WP_GEMM_BF16X3) return WP_EDTYPE;
+  FaceShapes fs{};
+  wp_status st = check_face(n1, n2, n3, p, trans_a, trans_b, &fs);
+  if (st != WP_OK) return st;
+  const bool x3 = gemm == WP_GEMM_BF16X3;
+  if (a_hi == nullptr || b_hi == nullptr || ch == nullptr) return WP_ENULL;
+  if (x3 && (a_lo == nullptr || b_lo == nullptr)) return WP_ENULL;
+  const Range rc = range_of(ch, fs.c, 4);
+  if (overlap(rc, range_of(a_hi, fs.a, 2)) || overlap(rc, range_of(b_hi, fs.b, 2))) return WP_EALIAS;
+  if (x3 && (overlap(rc, range_of(a_lo, fs.a, 2)) || overlap(rc, range_of(b_lo, fs.b, 2))))
+    return WP_EALIAS;
+  return from_hip(wp::launch_face_bf16(a_hi, a_lo, b_hi, b_lo, ch, n1, n2, n3, p, trans_a != 0,
+                                       trans_b != 0, x3, static_cast<hipStream_t>(stream)));
+}
+
+size_t w_product_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int L, int dtype,
+                           int gemm) {
+  if (check_modes(dtype, gemm) != WP_OK) return 0;
+  FaceShapes fs{};
+  if (check_face(n1, n2, n3, p, 0, 0, &fs) != WP_OK) return 0;
+  if (L < 0 || L > wp::kMaxLevels || p % (int64_t(1) << L) != 0) return 0;
+  return plan_product(fs, dtype, gemm).total;
+}
+
+wp_status w_product(const void* a, const void* b, void* c, int64_t n1, int64_t n2, int64_t n3,
+                    int64_t p, int L, int trans_a, int trans_b, int dtype, int gemm, void* ws,
+                    size_t ws_bytes, void* stream) {
+  wp_status st = check_modes(dtype, gemm);
+  if (st != WP_OK) return st;
+  FaceShapes fs{};
+  st = check_face(n1, n2, n3, p, trans_a, trans_b, &fs);
+  if (st != WP_OK) return st;
+  if (L < 0 || L > wp::kMaxLevels || p % (int64_t(1) << L) != 0) return WP_EINVAL;
+  if (a == nullptr || b == nullptr || c == nullptr || ws == nullptr) return WP_ENULL;
+  const ProductPlan pl = plan_product(fs, dtype, gemm);
+  if (ws_bytes < pl.total) return WP_EWORKSPACE;
+  const size_t es = dtype_size(dtype);
+  const Range ra = range_of(a, fs.a, es), rb = range_of(b, fs.b, es), rc = range_of(c, fs.c, es);
+  const Range rw{static_cast<const char*>(ws), static_cast<const char*>(ws) + ws_bytes};
+  if (overlap(rc, ra) || overlap(rc, rb) || overlap(rw, ra) || overlap(rw, rb) || overlap(rw, rc))
+    return WP_EALIAS;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = reinterpret_cast<char*>(wp::align_up(reinterpret_cast<uintptr_t>(ws), kAlign));
+  // Stored shapes: A is (p, n1, n2) or (p, n2, n1); the transform only sees
+  // n1*n2 positions per slice either way (Thm 2.1).
+  const int64_t Pa = n1 * n2, Pb = n2 * n3, Pc = n1 * n3;
+  hipError_t e = hipSuccess;
+  if (gemm == WP_GEMM_NATIVE) {
+    void* ah = base + pl.ah;
+    void* bh = base + pl.bh;
+    void* ch = base + pl.ch;
+    if (dtype == WP_F64) {
+      e = wp::launch_lift_f64(LiftKind::kForward, static_cast<const double*>(a), static_cast<double*>(ah), Pa, p, L, s);
+      if (e == hipSuccess) e = wp::launch_lift_f64(LiftKind::kForward, static_cast<const double*>(b), static_cast<double*>(bh), Pb, p, L, s);
+      if (e == hipSuccess) e = wp::launch_face_f64(static_cast<const double*>(ah), static_cast<const double*>(bh), static_cast<double*>(ch), n1, n2, n3, p, trans_a != 0, trans_b != 0, s);
+      if (e == hipSuccess) e = wp::launch_lift_f64(LiftKind::kInverse, static_cast<const double*>(ch), static_cast<double*>(c), Pc, p, L, s);
+    } else {
+      e = wp::launch_lift_f32(LiftKind::kForward, static_cast<const float*>(a), static_cast<float*>(ah), Pa, p, L, s);
+      if (e == hipSuccess) e = wp::launch_lift_f32(LiftKind::kForward, static_cast<const float*>(b), static_cast<float*>(bh), Pb, p, L, s);
+      if (e == hipSuccess) e = wp::launch_face_f32(static_cast<const float*>(ah), static_cast<const float*>(bh), static_cast<float*>(ch), n1, n2, n3, p, trans_a != 0, trans_b != 0, s);
+      if (e == hipSuccess) e = wp::launch_lift_f32(LiftKind::kInverse, static_cast<const float*>(ch), static_cast<float*>(c), Pc, p, L, s);
+    }
+  } else {
+    const bool x3 = gemm == WP_GEMM_BF16X3;
+    uint16_t* ahi = reinterpret_cast<uint16_t*>(base + pl.ah);
+    uint16_t* alo = x3 ? reinterpret_cast<uint16_t*>(base + pl.ah_lo) : nullptr;
+    uint16_t* bhi = reinterpret_cast<uint16_t*>(base + pl.bh);
+    uint16_t* blo = x3 ? reinterpret_cast<uint16_t*>(base + pl.bh_lo) : nullptr;
+    float* ch = reinterpret_cast<float*>(base + pl.ch);
+    e = wp::launch_lift_f32_split(LiftKind::kForward, static_cast<const float*>(a), ahi, alo, Pa, p, L, s);
+    if (e == hipSuccess) e = wp::launch_lift_f32_split(LiftKind::kForward, static_cast<const float*>(b), bhi, blo, Pb, p, L, s);
+    if (e == hipSuccess) e = wp::launch_face_bf16(ahi, alo, bhi, blo, ch, n1, n2, n3, p, trans_a != 0, trans_b != 0, x3, s);
+    if (e == hipSuccess) e = wp::launch_lift_f32(LiftKind::kInverse, ch, static_cast<float*>(c), Pc, p, L, s);
+  }
+  return from_hip(e);
+}
+
+size_t w_svd_workspace(int64_t n1, int64_t n2, int64_t p, int L, int k, int dtype) {
+  if (!valid_dtype(dtype)) return 0;
+  int64_t elems = 0;
+  if (check_tensor(n1, n2, p, L, &elems) != WP_OK) return 0;
+  if (k < 1 || k > n1 || k > n2 || n1 > 1024 || n2 > 1024) return 0;
+  return wp::svd_workspace_bytes(n1, n2, p, k, dtype);
+}
+
+wp_status w_svd(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k, void* uhat,
+                void* shat, void* vhat, void* ak, int max_sweeps, int32_t* info, double* orth_err,
+                int dtype, void* ws, size_t ws_bytes, void* stream) {
+  if (!valid_dtype(dtype)) return WP_EDTYPE;
+  int64_t elems = 0;
+  wp_status st = check_tensor(n1, n2, p, L, &elems);
+  if (st != WP_OK) return st;
+  if (k < 1 || k > n1 || k > n2 || n1 > 1024 || n2 > 1024) return WP_EINVAL;
+  if (a == nullptr || uhat == nullptr || shat == nullptr || vhat == nullptr || info == nullptr ||
+      ws == nullptr)
+    return WP_ENULL;
+  const size_t need = wp::svd_workspace_bytes(n1, n2, p, k, dtype);
+  if (ws_bytes < need) return WP_EWORKSPACE;
+  const size_t es = dtype_size(dtype);
+  const Range ra = range_of(a, elems, es);
+  const Range outs[] = {range_of(uhat, p * n1 * k, es), range_of(shat, p * k, es),
+                        range_of(vhat, p * n2 * k, es), range_of(ak, ak ? elems : 0, es),
+                        range_of(info, p, 4), range_of(orth_err, orth_err ? 2 : 0, 8),
+                        Range{static_cast<const char*>(ws), static_cast<const char*>(ws) + ws_bytes}};
+  constexpr int nout = sizeof(outs) / sizeof(outs[0]);
+  for (int i = 0; i < nout; ++i) {
+    if (overlap(outs[i], ra)) return WP_EALIAS;
+    for (int j = i + 1; j < nout; ++j)
+      if (overlap(outs[i], outs[j])) return WP_EALIAS;
+  }
+  return from_hip(wp::launch_svd(a, n1, n2, p, L, k, uhat, shat, vhat, ak, max_sweeps, info,
+                                 orth_err, dtype, ws, static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

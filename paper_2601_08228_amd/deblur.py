@@ -1,0 +1,40 @@
+"""Least-squares deblurring min_X ||K *_w X - Y||_F^2 by fixed-step gradient descent.
+
+The gradient 2 K^T *_w (K *_w X - Y) comes from the library's reverse-mode
+w-product (WProduct): forward lifting of K and X, face-product, inverse
+lifting, then W^{-T}, a transposed face-product and W^T.  The residual, the
+loss and the update are elementwise tensor operations on the device.
+"""
+
+import torch
+
+from .autograd import WProduct
+
+__all__ = ["lsq_gradient", "solve"]
+
+
+def lsq_gradient(k, x, y, L, gemm="native"):
+    """Gradient of ||K *_w X - Y||_F^2 with respect to X (device tensors)."""
+    xv = x.detach().clone().requires_grad_(True)
+    r = WProduct.apply(k, xv, L, gemm) - y
+    (r * r).sum().backward()
+    return xv.grad
+
+
+def solve(k, y, L, steps, eta, gemm="native", x0=None):
+    """Run `steps` iterations X <- X - eta * grad from X0 (zeros by default).
+
+    Returns the final iterate and the losses before each step (host floats,
+    read back once at the end).
+    """
+    x = torch.zeros_like(y) if x0 is None else x0.detach().clone()
+    losses = []
+    for _ in range(steps):
+        xv = x.requires_grad_(True)
+        r = WProduct.apply(k, xv, L, gemm) - y
+        loss = (r * r).sum()
+        loss.backward()
+        losses.append(loss.detach())
+        with torch.no_grad():
+            x = (xv - eta * xv.grad).detach()
+    return x, [float(v) for v in torch.stack(losses).cpu()]

@@ -13,7 +13,8 @@ spatially correlated abundance maps, values in [0, 1], few components.
 
 import numpy as np
 
-__all__ = ["normal", "uniform", "hsi_like", "gaussian_band", "stack_slices"]
+__all__ = ["normal", "uniform", "hsi_like", "gaussian_band", "stack_slices", "normal_device",
+           "uniform_device"]
 
 
 def normal(shape, seed, scale=1.0):
@@ -90,3 +91,19 @@ def gaussian_band(n, sigma=1.5, half_width=4):
 def stack_slices(mat, p):
     """Tensor whose p frontal slices all equal ``mat`` (shape (p, n1, n2))."""
     return np.repeat(np.asarray(mat, dtype=np.float64)[None], p, axis=0)
+
+
+def normal_device(shape, seed, device, dtype=None, scale=1.0):
+    """i.i.d. N(0, scale^2) drawn on the device by torch's seeded generator (for large inputs)."""
+    import torch
+    gen = torch.Generator(device=device).manual_seed(int(seed))
+    x = torch.randn(shape, generator=gen, device=device, dtype=dtype or torch.float32)
+    return x.mul_(scale) if scale != 1.0 else x
+
+
+def uniform_device(shape, seed, device, lo=-1.0, hi=1.0, dtype=None):
+    """i.i.d. U(lo, hi) drawn on the device by torch's seeded generator (for large inputs)."""
+    import torch
+    gen = torch.Generator(device=device).manual_seed(int(seed))
+    x = torch.rand(shape, generator=gen, device=device, dtype=dtype or torch.float32)
+    return x.mul_(hi - lo).add_(lo)

@@ -1,0 +1,221 @@
+"""Python binding of libwprod.so: the C entry points under the same names.
+
+Argument marshalling only: each function checks that its tensors are
+contiguous device tensors of a supported dtype, allocates outputs (and the
+workspace) with torch, and calls the library on torch's current stream.
+Tensors use the library layout: shape (p, n1, n2), frontal slices first.
+Split-precision coefficients are returned as torch.bfloat16 tensors holding
+the hi / lo parts.
+"""
+
+import collections
+import ctypes
+
+import torch
+
+from . import _lib
+
+__all__ = [
+    "w_transform", "w_itransform", "w_transform_adj", "w_itransform_adj",
+    "w_transform_split", "w_itransform_adj_split", "w_face_product",
+    "w_face_product_split", "w_product", "w_product_workspace", "w_svd",
+    "w_svd_workspace", "SvdResult",
+]
+
+_DT = {torch.float64: _lib.WP_F64, torch.float32: _lib.WP_F32}
+
+
+def _stream(t):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _dev_tensor(t, name, dtypes):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if t.device.type != "cuda":
+        raise ValueError("%s must be a device tensor (got %s)" % (name, t.device))
+    if t.dtype not in dtypes:
+        raise ValueError("%s has dtype %s; expected one of %s" % (name, t.dtype, dtypes))
+    if t.dim() != 3:
+        raise ValueError("%s must have shape (p, n1, n2)" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+def _lift(fn_name, x, L, out):
+    _dev_tensor(x, "x", tuple(_DT))
+    if out is None:
+        out = torch.empty_like(x)
+    else:
+        _dev_tensor(out, "out", (x.dtype,))
+        if out.shape != x.shape:
+            raise ValueError("out has the wrong shape")
+    p, n1, n2 = x.shape
+    with torch.cuda.device(x.device):
+        st = getattr(_lib.load(), fn_name)(_ptr(x), _ptr(out), n1, n2, p, int(L), _DT[x.dtype],
+                                           _stream(x))
+    _lib.check(fn_name, st)
+    return out
+
+
+def w_transform(x, L, out=None):
+    """Forward lifting W_[L] along mode 3 (Eq. (1)); coefficients in Eq. (1) order."""
+    return _lift("w_transform", x, L, out)
+
+
+def w_itransform(xhat, L, out=None):
+    """Inverse lifting W_[L]^{-1} (Alg. 1 inverse steps)."""
+    return _lift("w_itransform", xhat, L, out)
+
+
+def w_transform_adj(g, L, out=None):
+    """W_[L]^T applied to coefficient-space g (reverse-mode step)."""
+    return _lift("w_transform_adj", g, L, out)
+
+
+def w_itransform_adj(g, L, out=None):
+    """W_[L]^{-T} applied to spatial g (reverse-mode step)."""
+    return _lift("w_itransform_adj", g, L, out)
+
+
+def _lift_split(fn_name, x, L, with_lo):
+    _dev_tensor(x, "x", (torch.float32,))
+    hi = torch.empty(x.shape, dtype=torch.bfloat16, device=x.device)
+    lo = torch.empty(x.shape, dtype=torch.bfloat16, device=x.device) if with_lo else None
+    p, n1, n2 = x.shape
+    with torch.cuda.device(x.device):
+        st = getattr(_lib.load(), fn_name)(_ptr(x), _ptr(hi), _ptr(lo), n1, n2, p, int(L), _stream(x))
+    _lib.check(fn_name, st)
+    return hi, lo
+
+
+def w_transform_split(x, L, with_lo=True):
+    """Forward lifting of float32 x with bf16 hi/lo outputs (lo omitted if with_lo=False)."""
+    return _lift_split("w_transform_split", x, L, with_lo)
+
+
+def w_itransform_adj_split(g, L, with_lo=True):
+    """W^{-T} of float32 g with bf16 hi/lo outputs."""
+    return _lift_split("w_itransform_adj_split", g, L, with_lo)
+
+
+def _face_dims(a, b, trans_a, trans_b):
+    if a.shape[0] != b.shape[0]:
+        raise ValueError("operands have different numbers of slices")
+    p = a.shape[0]
+    n1, n2 = (a.shape[2], a.shape[1]) if trans_a else (a.shape[1], a.shape[2])
+    kb, n3 = (b.shape[2], b.shape[1]) if trans_b else (b.shape[1], b.shape[2])
+    if kb != n2:
+        raise ValueError("inner dimensions differ: %d vs %d" % (n2, kb))
+    return p, n1, n2, n3
+
+
+def w_face_product(ah, bh, trans_a=False, trans_b=False, out=None):
+    """Face-product (Def. 2.1): out[k] = op(ah[k]) @ op(bh[k]) on FP64 / FP32 MFMA."""
+    _dev_tensor(ah, "ah", tuple(_DT))
+    _dev_tensor(bh, "bh", (ah.dtype,))
+    p, n1, n2, n3 = _face_dims(ah, bh, trans_a, trans_b)
+    if out is None:
+        out = torch.empty((p, n1, n3), dtype=ah.dtype, device=ah.device)
+    else:
+        _dev_tensor(out, "out", (ah.dtype,))
+        if tuple(out.shape) != (p, n1, n3):
+            raise ValueError("out has the wrong shape")
+    with torch.cuda.device(ah.device):
+        st = _lib.load().w_face_product(_ptr(ah), _ptr(bh), _ptr(out), n1, n2, n3, p, int(trans_a),
+                                        int(trans_b), _DT[ah.dtype], _stream(ah))
+    _lib.check("w_face_product", st)
+    return out
+
+
+def w_face_product_split(a_hi, a_lo, b_hi, b_lo, trans_a=False, trans_b=False, gemm="bf16x3",
+                         out=None):
+    """Face-product of split operands on BF16 MFMA with FP32 accumulation (float32 result)."""
+    mode = _lib.GEMM_MODES[gemm]
+    if mode == 0:
+        raise ValueError("split face-product needs gemm='bf16' or 'bf16x3'")
+    _dev_tensor(a_hi, "a_hi", (torch.bfloat16,))
+    _dev_tensor(b_hi, "b_hi", (torch.bfloat16,))
+    if gemm == "bf16x3":
+        _dev_tensor(a_lo, "a_lo", (torch.bfloat16,))
+        _dev_tensor(b_lo, "b_lo", (torch.bfloat16,))
+    else:
+        a_lo = b_lo = None
+    p, n1, n2, n3 = _face_dims(a_hi, b_hi, trans_a, trans_b)
+    if out is None:
+        out = torch.empty((p, n1, n3), dtype=torch.float32, device=a_hi.device)
+    else:
+        _dev_tensor(out, "out", (torch.float32,))
+        if tuple(out.shape) != (p, n1, n3):
+            raise ValueError("out has the wrong shape")
+    with torch.cuda.device(a_hi.device):
+        st = _lib.load().w_face_product_split(_ptr(a_hi), _ptr(a_lo), _ptr(b_hi), _ptr(b_lo),
+                                              _ptr(out), n1, n2, n3, p, int(trans_a),
+                                              int(trans_b), mode, _stream(a_hi))
+    _lib.check("w_face_product_split", st)
+    return out
+
+
+def w_product_workspace(n1, n2, n3, p, L, dtype=torch.float32, gemm="native"):
+    return int(_lib.load().w_product_workspace(n1, n2, n3, p, int(L), _DT[dtype],
+                                               _lib.GEMM_MODES[gemm]))
+
+
+def w_product(a, b, L, trans_a=False, trans_b=False, gemm="native", out=None, workspace=None):
+    """w-product C = op(A) *_w op(B) (Def. 2.1, Alg. 1) in one library call."""
+    _dev_tensor(a, "a", tuple(_DT))
+    _dev_tensor(b, "b", (a.dtype,))
+    p, n1, n2, n3 = _face_dims(a, b, trans_a, trans_b)
+    mode = _lib.GEMM_MODES[gemm]
+    need = w_product_workspace(n1, n2, n3, p, L, a.dtype, gemm)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=a.device)
+    if out is None:
+        out = torch.empty((p, n1, n3), dtype=a.dtype, device=a.device)
+    with torch.cuda.device(a.device):
+        st = _lib.load().w_product(_ptr(a), _ptr(b), _ptr(out), n1, n2, n3, p, int(L), int(trans_a),
+                                   int(trans_b), _DT[a.dtype], mode, _ptr(workspace),
+                                   workspace.numel() * workspace.element_size(), _stream(a))
+    _lib.check("w_product", st)
+    return out
+
+
+SvdResult = collections.namedtuple("SvdResult", "uhat shat vhat ak info orth_err")
+
+
+def w_svd_workspace(n1, n2, p, L, k, dtype=torch.float32):
+    return int(_lib.load().w_svd_workspace(n1, n2, p, int(L), int(k), _DT[dtype]))
+
+
+def w_svd(a, L, k, max_sweeps=0, want_ak=True, want_orth=True, workspace=None):
+    """Truncated w-svd (Alg. 2): wavelet-domain factors, rank-k approximation, Jacobi info.
+
+    Returns SvdResult(uhat (p,n1,k), shat (p,k), vhat (p,n2,k), ak (p,n1,n2) or None,
+    info (p,) int32 device tensor, orth_err (2,) float64 device tensor or None).
+    Nothing is synchronised; info[k] < 0 marks a slice that did not converge.
+    """
+    _dev_tensor(a, "a", tuple(_DT))
+    p, n1, n2 = a.shape
+    k = int(k)
+    dev = a.device
+    uhat = torch.empty((p, n1, k), dtype=a.dtype, device=dev)
+    shat = torch.empty((p, k), dtype=a.dtype, device=dev)
+    vhat = torch.empty((p, n2, k), dtype=a.dtype, device=dev)
+    ak = torch.empty_like(a) if want_ak else None
+    info = torch.empty((p,), dtype=torch.int32, device=dev)
+    orth = torch.empty((2,), dtype=torch.float64, device=dev) if want_orth else None
+    need = w_svd_workspace(n1, n2, p, L, k, a.dtype)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    with torch.cuda.device(dev):
+        st = _lib.load().w_svd(_ptr(a), n1, n2, p, int(L), k, _ptr(uhat), _ptr(shat), _ptr(vhat),
+                               _ptr(ak), int(max_sweeps), _ptr(info), _ptr(orth), _DT[a.dtype],
+                               _ptr(workspace), workspace.numel() * workspace.element_size(),
+                               _stream(a))
+    _lib.check("w_svd", st)
+    return SvdResult(uhat, shat, vhat, ak, info, orth)

@@ -1,0 +1,147 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared symbol,
+and rejects invalid arguments before touching the GPU (no compute call is made)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wprod.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\**\s+\**(w_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2601_08228_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libwprod.so not built")
+    return _lib.load()
+
+
+def test_header_declares_expected_entry_points():
+    names = _declared_functions()
+    for must in ["w_transform", "w_itransform", "w_transform_adj", "w_itransform_adj",
+                 "w_transform_split", "w_itransform_adj_split", "w_face_product",
+                 "w_face_product_split", "w_product", "w_product_workspace", "w_svd",
+                 "w_svd_workspace", "w_status_string", "w_version"]:
+        assert must in names, must
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2601_08228_amd import _lib
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, name
+
+
+def test_status_strings(lib):
+    for code in [0, -1, -2, -3, -4, -5, -6, -7]:
+        s = lib.w_status_string(code).decode()
+        assert s.startswith("WP_")
+    assert lib.w_status_string(-99).decode() == "unknown wp_status"
+    assert lib.w_version() >= 100
+
+
+# Fake, never dereferenced addresses: every call below fails validation first.
+A = ctypes.c_void_p(0x100000)
+B = ctypes.c_void_p(0x200000)
+C = ctypes.c_void_p(0x300000)
+WS = ctypes.c_void_p(0x400000)
+NULL = None
+
+
+@pytest.mark.parametrize("fn", ["w_transform", "w_itransform", "w_transform_adj", "w_itransform_adj"])
+def test_transform_validation(lib, fn):
+    f = getattr(lib, fn)
+    assert f(A, B, 4, 4, 6, 2, 1, NULL) == -1          # p not a multiple of 2^L
+    assert f(A, B, 4, 4, 8, -1, 1, NULL) == -1         # negative level
+    assert f(A, B, 4, 4, 2048, 11, 1, NULL) == -1      # more than 10 levels
+    assert f(A, B, 0, 4, 8, 1, 1, NULL) == -1          # empty slice
+    assert f(A, B, 4, 4, 0, 0, 1, NULL) == -1          # no slices
+    assert f(A, B, 1 << 20, 1 << 20, 1 << 4, 1, 1, NULL) == -1  # too many elements
+    assert f(A, B, 4, 4, 8, 1, 7, NULL) == -4          # unknown dtype
+    assert f(NULL, B, 4, 4, 8, 1, 1, NULL) == -2
+    assert f(A, NULL, 4, 4, 8, 1, 1, NULL) == -2
+    # out overlaps in (4*4*8 floats = 512 bytes)
+    assert f(A, ctypes.c_void_p(0x100000 + 256), 4, 4, 8, 1, 1, NULL) == -3
+    assert f(A, A, 4, 4, 8, 1, 0, NULL) == -3
+
+
+def test_split_validation(lib):
+    for fn in ("w_transform_split", "w_itransform_adj_split"):
+        f = getattr(lib, fn)
+        assert f(A, B, C, 4, 4, 6, 2, NULL) == -1
+        assert f(NULL, B, C, 4, 4, 8, 2, NULL) == -2
+        assert f(A, NULL, C, 4, 4, 8, 2, NULL) == -2
+        assert f(A, B, ctypes.c_void_p(0x200000 + 64), 4, 4, 8, 2, NULL) == -3  # hi/lo overlap
+        assert f(A, ctypes.c_void_p(0x100000 + 64), NULL, 4, 4, 8, 2, NULL) == -3
+
+
+def test_face_product_validation(lib):
+    f = lib.w_face_product
+    assert f(A, B, C, 4, 5, 6, 3, 0, 0, 5, NULL) == -4
+    assert f(A, B, C, 4, 0, 6, 3, 0, 0, 1, NULL) == -1
+    assert f(A, B, C, 4, 5, 6, 3, 2, 0, 1, NULL) == -1     # bad flag
+    assert f(A, NULL, C, 4, 5, 6, 3, 0, 0, 1, NULL) == -2
+    assert f(A, B, ctypes.c_void_p(0x200000 + 4), 4, 5, 6, 3, 0, 0, 1, NULL) == -3
+    g = lib.w_face_product_split
+    assert g(A, NULL, B, NULL, C, 4, 5, 6, 3, 0, 0, 0, NULL) == -4  # native mode invalid here
+    assert g(A, NULL, B, NULL, C, 4, 5, 6, 3, 0, 0, 2, NULL) == -2  # bf16x3 needs lo planes
+    assert g(NULL, NULL, B, NULL, C, 4, 5, 6, 3, 0, 0, 1, NULL) == -2
+    assert g(A, NULL, B, NULL, ctypes.c_void_p(0x100000), 4, 5, 6, 3, 0, 0, 1, NULL) == -3
+
+
+def test_product_validation_and_workspace(lib):
+    ws_f32 = lib.w_product_workspace(4, 5, 6, 8, 3, 1, 0)
+    ws_x3 = lib.w_product_workspace(4, 5, 6, 8, 3, 1, 2)
+    ws_f64 = lib.w_product_workspace(4, 5, 6, 8, 3, 0, 0)
+    assert ws_f32 >= 8 * (20 + 30 + 24) * 4
+    assert ws_f64 >= 8 * (20 + 30 + 24) * 8
+    assert ws_x3 >= 8 * (20 + 30) * 4 + 8 * 24 * 4
+    assert lib.w_product_workspace(4, 5, 6, 8, 3, 0, 2) == 0     # bf16x3 needs F32
+    assert lib.w_product_workspace(4, 5, 6, 6, 3, 1, 0) == 0     # bad level
+    f = lib.w_product
+    args = (4, 5, 6, 8, 3, 0, 0, 1, 0)
+    assert f(A, B, C, *args, WS, ws_f32 - 1, NULL) == -5
+    assert f(A, B, C, *args, NULL, ws_f32, NULL) == -2
+    assert f(A, B, C, 4, 5, 6, 8, 3, 0, 0, 0, 2, WS, 1 << 30, NULL) == -4
+    assert f(A, B, C, 4, 5, 6, 8, 3, 0, 0, 1, 9, WS, 1 << 30, NULL) == -4
+    assert f(A, B, C, 4, 5, 6, 6, 3, 0, 0, 1, 0, WS, 1 << 30, NULL) == -1
+    assert f(A, B, A, *args, WS, ws_f32, NULL) == -3                       # C aliases A
+    assert f(A, B, C, *args, ctypes.c_void_p(0x300000 + 16), ws_f32, NULL) == -3  # ws overlaps C
+
+
+def test_svd_validation(lib):
+    need = lib.w_svd_workspace(8, 6, 16, 2, 3, 1)
+    assert need > 0
+    assert lib.w_svd_workspace(8, 6, 16, 2, 7, 1) == 0           # k > min(n1, n2)
+    assert lib.w_svd_workspace(2048, 6, 16, 2, 3, 1) == 0        # n1 > 1024
+    f = lib.w_svd
+    U, S, V, AK = (ctypes.c_void_p(0x500000), ctypes.c_void_p(0x600000),
+                   ctypes.c_void_p(0x700000), ctypes.c_void_p(0x800000))
+    INFO, ORTH = ctypes.c_void_p(0x900000), ctypes.c_void_p(0xA00000)
+    W = ctypes.c_void_p(0x10000000)
+    assert f(A, 8, 6, 16, 2, 0, U, S, V, AK, 0, INFO, ORTH, 1, W, need, NULL) == -1
+    assert f(A, 8, 6, 16, 2, 7, U, S, V, AK, 0, INFO, ORTH, 1, W, need, NULL) == -1
+    assert f(A, 8, 6, 12, 3, 3, U, S, V, AK, 0, INFO, ORTH, 1, W, need, NULL) == -1
+    assert f(A, 8, 6, 16, 2, 3, U, S, V, AK, 0, INFO, ORTH, 3, W, need, NULL) == -4
+    assert f(A, 8, 6, 16, 2, 3, U, S, V, AK, 0, NULL, ORTH, 1, W, need, NULL) == -2
+    assert f(A, 8, 6, 16, 2, 3, U, S, V, AK, 0, INFO, ORTH, 1, W, need - 1, NULL) == -5
+    assert f(A, 8, 6, 16, 2, 3, A, S, V, AK, 0, INFO, ORTH, 1, W, need, NULL) == -3
+    assert f(A, 8, 6, 16, 2, 3, U, U, V, AK, 0, INFO, ORTH, 1, W, need, NULL) == -3
+
+
+def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_2601_08228_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.load()

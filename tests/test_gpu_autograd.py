@@ -1,0 +1,106 @@
+"""GPU parity of the hand-written adjoint (torch.autograd.Function) and the deblurring solve."""
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from gpu_helpers import device, to_dev, host, cast, rel_fro
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wp():
+    device()
+    import paper_2601_08228_amd as wp
+    return wp
+
+
+def test_gradcheck_fp64_crop(wp):
+    # Central finite differences in FP64 on the 16x16x8 crop of the deblurring
+    # problem: K = 8 copies of the 16x16 Gaussian band, X[:8, :16, :16].
+    import torch
+    from paper_2601_08228_amd import synth
+    k = synth.stack_slices(synth.gaussian_band(16), 8)
+    x = synth.hsi_like(16, 16, 8, seed=5)
+    tk = to_dev(k, torch.float64).requires_grad_(True)
+    tx = to_dev(x, torch.float64).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda a, b: wp.w_product_ad(a, b, 3), (tk, tx),
+                                    eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+@pytest.mark.parametrize("gemm,tol", [("native", 1e-5), ("bf16x3", 1e-5), ("bf16", 1e-2)])
+def test_vjp_f32_vs_oracle(wp, gemm, tol):
+    import torch
+    rng = np.random.default_rng(3)
+    p, L = 32, 4
+    a = cast(rng.standard_normal((p, 96, 80)), np.float32)
+    b = cast(rng.standard_normal((p, 80, 72)), np.float32)
+    g = cast(rng.standard_normal((p, 96, 72)), np.float32)
+    ta = to_dev(a, torch.float32).requires_grad_(True)
+    tb = to_dev(b, torch.float32).requires_grad_(True)
+    c = wp.w_product_ad(ta, tb, L, gemm)
+    c.backward(to_dev(g, torch.float32))
+    da, db = orc.w_product_vjp(a, b, g, L)
+    assert rel_fro(host(c), orc.w_product(a, b, L)) <= tol
+    assert rel_fro(host(ta.grad), da) <= tol
+    assert rel_fro(host(tb.grad), db) <= tol
+
+
+def test_vjp_f64_vs_oracle(wp):
+    import torch
+    rng = np.random.default_rng(4)
+    p, L = 16, 3
+    a, b, g = (rng.standard_normal(s) for s in [(p, 40, 30), (p, 30, 20), (p, 40, 20)])
+    ta = to_dev(a, torch.float64).requires_grad_(True)
+    tb = to_dev(b, torch.float64).requires_grad_(True)
+    wp.w_product_ad(ta, tb, L).backward(to_dev(g, torch.float64))
+    da, db = orc.w_product_vjp(a, b, g, L)
+    assert rel_fro(host(ta.grad), da) <= 1e-12
+    assert rel_fro(host(tb.grad), db) <= 1e-12
+
+
+def test_only_requested_gradients(wp):
+    import torch
+    a = to_dev(np.ones((4, 3, 3)), torch.float64).requires_grad_(True)
+    b = to_dev(np.ones((4, 3, 3)), torch.float64)
+    wp.w_product_ad(a, b, 2).sum().backward()
+    assert a.grad is not None and b.grad is None
+
+
+def _deblur_problem(n, p, seed):
+    from paper_2601_08228_amd import synth
+    g = synth.gaussian_band(n)
+    k = cast(synth.stack_slices(g, p), np.float32)
+    x = synth.hsi_like(n, n, p, seed=seed)
+    noise = synth.normal((p, n, n), seed=seed + 100, scale=0.01)
+    y = cast(orc.w_product(k, x, 3) + noise, np.float32)
+    eta = 1.0 / (2.0 * np.linalg.norm(g, 2) ** 2)
+    return k, x, y, eta
+
+
+def test_deblur_gradient_full_size(wp):
+    # 256x256x128 blur operator and hyperspectral-like tensor: the FP32 gradient at a
+    # nonzero point against the oracle gradient (<= 1e-5).
+    import torch
+    from paper_2601_08228_amd import deblur
+    k, x, y, _ = _deblur_problem(256, 128, seed=5)
+    x0 = cast(0.5 * x, np.float32)
+    grad = deblur.lsq_gradient(to_dev(k, torch.float32), to_dev(x0, torch.float32),
+                               to_dev(y, torch.float32), 3)
+    assert rel_fro(host(grad), orc.lsq_grad(k, x0, y, 3)) <= 1e-5
+
+
+@pytest.mark.parametrize("gemm", ["native", "bf16x3"])
+def test_deblur_trajectory(wp, gemm):
+    # 50 fixed-step iterations at 64x64x128 (the full 256x256 trajectory is in the
+    # benchmark); iterate and loss curve against the oracle trajectory.
+    import torch
+    from paper_2601_08228_amd import deblur
+    k, x, y, eta = _deblur_problem(64, 128, seed=6)
+    xs, losses = deblur.solve(to_dev(k, torch.float32), to_dev(y, torch.float32), 3, steps=50,
+                              eta=eta, gemm=gemm)
+    x_ref, loss_ref = orc.deblur_gd(k, y, 3, 50, eta)
+    assert rel_fro(host(xs), x_ref) <= 1e-5
+    np.testing.assert_allclose(losses, loss_ref[:len(losses)], rtol=1e-4)
+    assert losses[-1] < losses[0]

@@ -1,0 +1,98 @@
+"""GPU parity of the face-product GEMMs (FP64, FP32, BF16, bf16x3 MFMA) against the oracle."""
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from gpu_helpers import device, to_dev, host, cast, rel_fro, bf16_rne
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def wp():
+    device()
+    import paper_2601_08228_amd as wp
+    return wp
+
+
+def _operands(p, m, k, n, ta, tb, seed, dist="normal"):
+    rng = np.random.default_rng(seed)
+    draw = rng.standard_normal if dist == "normal" else (lambda s: rng.uniform(-1, 1, s))
+    a = draw((p, k, m) if ta else (p, m, k))
+    b = draw((p, n, k) if tb else (p, k, n))
+    return a, b
+
+
+# (p, m, k, n): several tiles plus ragged tails in every dimension, single-tile,
+# degenerate 1-wide dimensions, and K shorter than one K-tile.
+SHAPES = [(3, 130, 70, 200), (2, 64, 64, 64), (1, 1, 1, 1), (5, 17, 3, 9), (4, 257, 33, 129),
+          (2, 300, 520, 260), (16, 32, 24, 20), (1, 7, 1000, 5)]
+TRANS = [(False, False), (True, False), (False, True), (True, True)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("tt", TRANS)
+def test_f64(wp, shape, tt):
+    import torch
+    p, m, k, n = shape
+    a, b = _operands(p, m, k, n, *tt, seed=m + k)
+    out = host(wp.w_face_product(to_dev(a, torch.float64), to_dev(b, torch.float64), *tt))
+    ref = orc.face(a, b, *tt)
+    # FP64 MFMA with FP64 accumulation: a K-term dot product, error ~ K u64.
+    assert rel_fro(out, ref) <= 1e-15 * max(k, 8)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("tt", TRANS)
+def test_f32(wp, shape, tt):
+    import torch
+    p, m, k, n = shape
+    a, b = _operands(p, m, k, n, *tt, seed=m * 3 + n)
+    a, b = cast(a, np.float32), cast(b, np.float32)
+    out = host(wp.w_face_product(to_dev(a, torch.float32), to_dev(b, torch.float32), *tt))
+    assert rel_fro(out, orc.face(a, b, *tt)) <= 1e-7 * max(np.sqrt(k), 4)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("tt", TRANS)
+@pytest.mark.parametrize("mode", ["bf16", "bf16x3"])
+def test_split(wp, shape, tt, mode):
+    # Operands are split by the lifting epilogue at L = 0 (no transform), so the
+    # products are of the input values themselves.
+    import torch
+    p, m, k, n = shape
+    a, b = _operands(p, m, k, n, *tt, seed=m + 2 * n, dist="uniform")
+    a, b = cast(a, np.float32), cast(b, np.float32)
+    ahi, alo = wp.w_transform_split(to_dev(a, torch.float32), 0)
+    bhi, blo = wp.w_transform_split(to_dev(b, torch.float32), 0)
+    out = host(wp.w_face_product_split(ahi, alo, bhi, blo, *tt, gemm=mode))
+    a_hi = bf16_rne(a).astype(np.float64)
+    b_hi = bf16_rne(b).astype(np.float64)
+    a_lo = bf16_rne((a - a_hi).astype(np.float32)).astype(np.float64)
+    b_lo = bf16_rne((b - b_hi).astype(np.float32)).astype(np.float64)
+    if mode == "bf16":
+        exact = orc.face(a_hi, b_hi, *tt)          # the products the mode defines
+        assert rel_fro(out, exact) <= 1e-7 * max(np.sqrt(k), 4)
+        assert rel_fro(out, orc.face(a, b, *tt)) <= 1e-2
+    else:
+        exact = orc.face(a_hi, b_hi, *tt) + orc.face(a_hi, b_lo, *tt) + orc.face(a_lo, b_hi, *tt)
+        assert rel_fro(out, exact) <= 1e-7 * max(np.sqrt(k), 4)
+        assert rel_fro(out, orc.face(a, b, *tt)) <= 1e-5
+
+
+def test_deterministic(wp):
+    import torch
+    a, b = _operands(8, 200, 300, 100, False, False, seed=1)
+    da, db = to_dev(a, torch.float32), to_dev(b, torch.float32)
+    r1 = host(wp.w_face_product(da, db))
+    r2 = host(wp.w_face_product(da, db))
+    assert np.array_equal(r1, r2)
+
+
+def test_unaligned_pitch_uses_scalar_loads(wp):
+    # K = 3 makes the row pitch 12 bytes: the 16-byte load path must not be used.
+    import torch
+    a, b = _operands(6, 45, 3, 37, False, False, seed=2)
+    out = host(wp.w_face_product(to_dev(a, torch.float64), to_dev(b, torch.float64)))
+    assert rel_fro(out, orc.face(a, b)) <= 1e-15
