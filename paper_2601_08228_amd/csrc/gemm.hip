@@ -93,7 +93,10 @@ struct Dims {
   static constexpr int LDS_BYTES = 2 * STAGE_BYTES;
 };
 
-__device__ __forceinline__ int swz_chunk(int row, int c) { return c ^ ((row >> 1) & 3); }
+// Reads of 8 consecutive rows (MFMA fragments) stay conflict-free through the
+// (row >> 1) term; the (row >> 3) term spreads the transposed-path writes, in
+// which the lanes of a wave write rows 8 apart.
+__device__ __forceinline__ int swz_chunk(int row, int c) { return c ^ (((row >> 1) ^ (row >> 3)) & 3); }
 
 __device__ __forceinline__ int lds_off(int row, int c) {
   return row * (16 * kChunksPerRow) + swz_chunk(row, c) * 16;
@@ -124,10 +127,11 @@ __device__ __forceinline__ void mma_bf16(const u32x4& a, const u32x4& b, f32x16&
 }
 
 // ---- global -> register staging -------------------------------------------
-// One operand tile: R rows (M or N) by BK columns of K.  K_CONTIG: the stored
-// matrix has K contiguous (row pitch ld along R); otherwise R is contiguous
-// and the pitch ld runs along K.
-template <class Cfg, int R, bool K_CONTIG>
+// One operand tile in NPL planes (hi, and lo for the split products): R rows
+// (M or N) by BK columns of K.  K_CONTIG: the stored matrix has K contiguous
+// (row pitch ld along R); otherwise R is contiguous and the pitch ld runs
+// along K.  The work items of all planes are dealt over the whole workgroup.
+template <class Cfg, int R, bool K_CONTIG, int NPL>
 struct TileLoader {
   using In = typename Cfg::In;
   static constexpr int CH = Cfg::CH;
@@ -135,7 +139,8 @@ struct TileLoader {
   // Work items per plane: K-contiguous -> one chunk each; otherwise one
   // CH x CH micro-block each.
   static constexpr int ITEMS = K_CONTIG ? R * kChunksPerRow : (BK / CH) * (R / CH);
-  static constexpr int PER_THREAD = (ITEMS + kThreads - 1) / kThreads;
+  static constexpr int TOTAL = ITEMS * NPL;
+  static constexpr int PER_THREAD = (TOTAL + kThreads - 1) / kThreads;
   static constexpr int REGS = K_CONTIG ? 1 : CH;  // 16-byte chunks per item
   u32x4 buf[PER_THREAD][REGS];
 
@@ -146,24 +151,27 @@ struct TileLoader {
     return K_CONTIG ? base[int64_t(r) * ld + k] : base[int64_t(k) * ld + r];
   }
 
-  // base points at element (row 0, k 0) of the tile; rlim/klim = rows/K left.
-  __device__ __forceinline__ void load(const In* __restrict__ base, int64_t ld, int rlim, int klim,
+  // base[p] points at element (row 0, k 0) of plane p; rlim/klim = rows/K left.
+  __device__ __forceinline__ void load(const In* const* base, int64_t ld, int rlim, int klim,
                                        bool vec_ok) {
     const int tid = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
-      const int item = tid + i * kThreads;
-      if (ITEMS % kThreads != 0 && item >= ITEMS) break;
+      const int all = tid + i * kThreads;
+      if (TOTAL % kThreads != 0 && all >= TOTAL) break;
+      const int plane = NPL == 1 ? 0 : all / ITEMS;
+      const int item = NPL == 1 ? all : all % ITEMS;
+      const In* b = base[plane];
       if constexpr (K_CONTIG) {
         const int r = item / kChunksPerRow;
         const int c = item % kChunksPerRow;
         const int k0 = c * CH;
         if (vec_ok && r < rlim && k0 + CH <= klim) {
-          buf[i][0] = *reinterpret_cast<const u32x4*>(base + int64_t(r) * ld + k0);
+          buf[i][0] = *reinterpret_cast<const u32x4*>(b + int64_t(r) * ld + k0);
         } else {
           In tmp[CH];
 #pragma unroll
-          for (int e = 0; e < CH; ++e) tmp[e] = elem(base, ld, r, k0 + e, rlim, klim);
+          for (int e = 0; e < CH; ++e) tmp[e] = elem(b, ld, r, k0 + e, rlim, klim);
           __builtin_memcpy(&buf[i][0], tmp, 16);
         }
       } else {
@@ -176,11 +184,11 @@ struct TileLoader {
         for (int e = 0; e < CH; ++e) {
           const int k = k0 + e;
           if (vec_ok && k < klim && r0 + CH <= rlim) {
-            buf[i][e] = *reinterpret_cast<const u32x4*>(base + int64_t(k) * ld + r0);
+            buf[i][e] = *reinterpret_cast<const u32x4*>(b + int64_t(k) * ld + r0);
           } else {
             In tmp[CH];
 #pragma unroll
-            for (int f = 0; f < CH; ++f) tmp[f] = elem(base, ld, r0 + f, k, rlim, klim);
+            for (int f = 0; f < CH; ++f) tmp[f] = elem(b, ld, r0 + f, k, rlim, klim);
             __builtin_memcpy(&buf[i][e], tmp, 16);
           }
         }
@@ -188,17 +196,21 @@ struct TileLoader {
     }
   }
 
-  // Write the staged items into an LDS plane (rows of BK K-values).
-  __device__ __forceinline__ void store(char* __restrict__ lds) const {
+  // Write the staged items into the LDS planes (rows of BK K-values); plane p
+  // starts plane_bytes * p after lds.
+  __device__ __forceinline__ void store(char* __restrict__ lds, int plane_bytes) const {
     const int tid = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
-      const int item = tid + i * kThreads;
-      if (ITEMS % kThreads != 0 && item >= ITEMS) break;
+      const int all = tid + i * kThreads;
+      if (TOTAL % kThreads != 0 && all >= TOTAL) break;
+      const int plane = NPL == 1 ? 0 : all / ITEMS;
+      const int item = NPL == 1 ? all : all % ITEMS;
+      char* dst = lds + plane * plane_bytes;
       if constexpr (K_CONTIG) {
         const int r = item / kChunksPerRow;
         const int c = item % kChunksPerRow;
-        *reinterpret_cast<u32x4*>(lds + lds_off(r, c)) = buf[i][0];
+        *reinterpret_cast<u32x4*>(dst + lds_off(r, c)) = buf[i][0];
       } else {
         constexpr int RB = R / CH;
         const int kb = item / RB;
@@ -216,7 +228,7 @@ struct TileLoader {
           for (int e = 0; e < CH; ++e) col[e] = m[e][f];
           u32x4 v;
           __builtin_memcpy(&v, col, 16);
-          *reinterpret_cast<u32x4*>(lds + lds_off(r0 + f, kb)) = v;
+          *reinterpret_cast<u32x4*>(dst + lds_off(r0 + f, kb)) = v;
         }
       }
     }
@@ -284,32 +296,29 @@ __global__ __launch_bounds__(kThreads, 1) void face_gemm_kernel(GemmArgs args) {
     return TB ? base + int64_t(n0) * args.ldb + k0 : base + int64_t(k0) * args.ldb + n0;
   };
 
-  TileLoader<Cfg, BM, !TA> la_hi, la_lo;
-  TileLoader<Cfg, BN, TB> lb_hi, lb_lo;
+  constexpr int NPL = USE_LO ? 2 : 1;
+  TileLoader<Cfg, BM, !TA, NPL> la;
+  TileLoader<Cfg, BN, TB, NPL> lb;
 
   const int rlim_a = args.m - m0;
   const int rlim_b = args.n - n0;
   const bool va = args.vec_a != 0;
   const bool vb = args.vec_b != 0;
 
+  // LDS stage layout: A hi | A lo | B hi | B lo (lo planes only for bf16x3).
+  constexpr int A_PLANES = D::A_BYTES * NPL;
   auto issue_loads = [&](int k0) {
     const int klim = args.k - k0;
-    la_hi.load(a_origin(a_hi, k0), args.lda, rlim_a, klim, va);
-    lb_hi.load(b_origin(b_hi, k0), args.ldb, rlim_b, klim, vb);
-    if constexpr (USE_LO) {
-      la_lo.load(a_origin(a_lo, k0), args.lda, rlim_a, klim, va);
-      lb_lo.load(b_origin(b_lo, k0), args.ldb, rlim_b, klim, vb);
-    }
+    const In* pa[2] = {a_origin(a_hi, k0), USE_LO ? a_origin(a_lo, k0) : nullptr};
+    const In* pb[2] = {b_origin(b_hi, k0), USE_LO ? b_origin(b_lo, k0) : nullptr};
+    la.load(pa, args.lda, rlim_a, klim, va);
+    lb.load(pb, args.ldb, rlim_b, klim, vb);
   };
   auto stage_ptr = [&](int stage) { return smem + stage * D::STAGE_BYTES; };
   auto commit = [&](int stage) {
     char* s = stage_ptr(stage);
-    la_hi.store(s);
-    lb_hi.store(s + D::A_BYTES);
-    if constexpr (USE_LO) {
-      la_lo.store(s + D::A_BYTES + D::B_BYTES);
-      lb_lo.store(s + 2 * D::A_BYTES + D::B_BYTES);
-    }
+    la.store(s, D::A_BYTES);
+    lb.store(s + A_PLANES, D::B_BYTES);
   };
 
   const int lane = threadIdx.x & 63;
@@ -338,9 +347,9 @@ __global__ __launch_bounds__(kThreads, 1) void face_gemm_kernel(GemmArgs args) {
 
     const char* s = stage_ptr(cur);
     const char* sa_hi = s;
-    const char* sb_hi = s + D::A_BYTES;
-    const char* sa_lo = s + D::A_BYTES + D::B_BYTES;
-    const char* sb_lo = s + 2 * D::A_BYTES + D::B_BYTES;
+    const char* sa_lo = s + D::A_BYTES;
+    const char* sb_hi = s + A_PLANES;
+    const char* sb_lo = s + A_PLANES + D::B_BYTES;
 #pragma unroll
     for (int kg = 0; kg < D::KG; ++kg) {
       const int c = kg * G + lgrp;

@@ -2,18 +2,29 @@
 // one-sided (Hestenes) Jacobi, rank-k rebuild on the face-product GEMM, and
 // the inverse lifting.
 //
-// Jacobi: one workgroup owns one coefficient slice.  The slice is copied into
-// a column-major working matrix W (the slice itself when n1 >= n2, its
-// transpose otherwise, so that W has mr = max(n1, n2) rows and nc = min(n1, n2)
-// columns) and V starts as the identity.  A sweep visits every column pair
-// once, in nc_pad - 1 rounds of nc_pad/2 disjoint pairs (round-robin
-// tournament, one dummy column when nc is odd).  Each wavefront takes a batch
-// of pairs of the round, issues all their column loads at once, forms
-// alpha = |w_i|^2, beta = |w_j|^2, gamma = w_i.w_j in FP64 with wavefront
-// reductions, and applies the rotation (angle in FP64) to W and V.  A pair is
-// rotated when |gamma| > tol * sqrt(alpha * beta), tol = sqrt(mr) * unit
-// roundoff of the data type; the slice has converged after a sweep with no
-// rotation.  Columns live in the workspace, so they stay in the L2/MALL.
+// Jacobi: one workgroup owns one coefficient slice, viewed as a matrix W with
+// mr = max(n1, n2) rows and nc = min(n1, n2) columns (the slice itself when
+// n1 >= n2, its transpose otherwise); V starts as the identity.  A sweep
+// visits every column pair once, as a round-robin tournament: nc_pad - 1
+// rounds of nc_pad / 2 disjoint pairs.  For each pair, alpha = |w_i|^2,
+// beta = |w_j|^2 and gamma = w_i.w_j are formed in FP64, and when
+// |gamma| > tol * sqrt(alpha * beta) (tol = sqrt(mr) * unit roundoff of the
+// data type) the rotation angle is computed in FP64 and the rotation is
+// applied to columns i, j of W and V in the data type.  A slice has converged
+// after a sweep without rotation.
+//
+// Register-resident kernel (mr <= 256, nc <= 256): every wavefront keeps S
+// column pairs of W in registers, one pair slot per tournament pair.  Slot q
+// holds tournament positions q (top) and NP-1-q (bottom); between rounds the
+// columns advance one step around the circle of positions 1..NP-1 (position 0
+// is fixed), which is a register shift inside a wavefront plus one column in
+// each direction through LDS between neighbouring wavefronts.  The FP64 dot
+// products of a batch of pairs are reduced with one reduce-scatter butterfly,
+// the angles of the batch are computed side by side in one lane per pair and
+// broadcast with readlane.  V lives in the workspace (L2-resident) and is
+// updated one round behind, so its loads overlap the next batch's work.
+// A general kernel keeps W in the workspace as well and covers the larger
+// shapes.
 //
 // Afterwards sigma_i = |w_i| (FP64), the columns are ranked by decreasing
 // sigma (ties by index), the k leading ones are normalised into U, signs are
@@ -63,9 +74,128 @@ struct SvdDims {
   int trans;  // W = slice^T (n1 < n2)
 };
 
-// RPL: rows per lane (mr <= 64 * RPL).
+// Rotation that zeroes w_i.w_j, all in FP64.  With d = beta - alpha the
+// tangent t = sign(d) * 2 gamma / (|d| + sqrt(d^2 + 4 gamma^2)) is the smaller
+// root of t^2 + 2 zeta t - 1 = 0, zeta = d / (2 gamma) (Rutishauser's choice);
+// c = 1 / sqrt(1 + t^2), s = c t.
+// Returns 0: below the threshold (c = 1, s = 0), 1: rotate, 2: non-finite input.
+__device__ __forceinline__ int rotation(double al, double be, double ga, double tol, double& c,
+                                        double& s) {
+  c = 1.0;
+  s = 0.0;
+  if (!(isfinite(al) && isfinite(be) && isfinite(ga))) return 2;
+  if (!(ga * ga > tol * tol * (al * be))) return 0;
+  const double d = be - al;
+  const double g2 = 2.0 * ga;
+  const double t = copysign(1.0, d) * g2 / (fabs(d) + sqrt(fma(d, d, g2 * g2)));
+  c = rsqrt(fma(t, t, 1.0));
+  s = c * t;
+  return 1;
+}
+
+// Singular values, ranking and the k leading factors from the converged W and
+// V (column c of W at W + c*mr, of V at V + c*nc).  Called by every thread of
+// the workgroup.  With V == nullptr only the factor taken from W is written
+// (U when n1 >= n2, vhat otherwise; U * sigma too in the first case); the
+// other one is recovered afterwards from the coefficients (recover_kernel).
+template <typename T>
+__device__ void emit_factors(const T* __restrict__ W, const T* __restrict__ V, const SvdDims& d,
+                             int slice, T* __restrict__ uhat, T* __restrict__ shat,
+                             T* __restrict__ vhat, T* __restrict__ us, double* s_sigma,
+                             int* s_order) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int mr = d.mr, nc = d.nc;
+  for (int c = wave; c < nc; c += kJacobiWaves) {
+    double acc = 0;
+    for (int row = lane; row < mr; row += 64) {
+      const double x = double(W[int64_t(c) * mr + row]);
+      acc = fma(x, x, acc);
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) s_sigma[c] = sqrt(acc);
+  }
+  __syncthreads();
+  // Rank by a strict total order: larger sigma first, NaN after every number,
+  // ties (and NaNs) by column index; the ranks are therefore a permutation.
+  for (int c = threadIdx.x; c < nc; c += kJacobiThreads) {
+    const double sc = s_sigma[c];
+    const bool nan_c = sc != sc;
+    int rank = 0;
+    for (int o = 0; o < nc; ++o) {
+      const double so = s_sigma[o];
+      const bool nan_o = so != so;
+      const bool before = nan_o ? (nan_c && o < c)
+                                : (nan_c || so > sc || (so == sc && o < c));
+      rank += before;
+    }
+    s_order[rank] = c;
+  }
+  __syncthreads();
+
+  // U column i has n1 entries, V column i has n2 entries.  Without transposition
+  // U = W_c / sigma (mr = n1 rows) and V = V_c (nc = n2 rows); with it the roles swap.
+  const int k = d.k;
+  T* U = uhat + int64_t(slice) * d.n1 * k;
+  T* Vo = vhat + int64_t(slice) * d.n2 * k;
+  T* Us = us + int64_t(slice) * d.n1 * k;
+  for (int i = wave; i < k; i += kJacobiWaves) {
+    const int c = s_order[i];
+    const double sg = s_sigma[c];
+    const double inv = sg > 0 ? 1.0 / sg : 0.0;
+    if (V == nullptr && d.trans) {
+      // W holds the transposed slice: W_c / sigma is a right singular vector;
+      // its sign follows the recovered U column.
+      for (int row = lane; row < d.n2; row += 64)
+        Vo[int64_t(row) * k + i] = T(double(W[int64_t(c) * mr + row]) * inv);
+      if (lane == 0) shat[int64_t(slice) * k + i] = T(sg);
+      continue;
+    }
+    auto ucol = [&](int row) -> double {
+      return d.trans ? double(V[int64_t(c) * nc + row]) : double(W[int64_t(c) * mr + row]) * inv;
+    };
+    auto vcol = [&](int row) -> double {
+      return d.trans ? double(W[int64_t(c) * mr + row]) * inv : double(V[int64_t(c) * nc + row]);
+    };
+    // Largest |U| entry, lowest row on ties.
+    double best = -1.0;
+    int brow = 0x7fffffff;
+    double bval = 0;
+    for (int row = lane; row < d.n1; row += 64) {
+      const double x = ucol(row);
+      const double ax = fabs(x);
+      if (ax > best) {
+        best = ax;
+        brow = row;
+        bval = x;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const int orow = __shfl_xor(brow, o, 64);
+      const double ov = __shfl_xor(bval, o, 64);
+      if (ob > best || (ob == best && orow < brow)) {
+        best = ob;
+        brow = orow;
+        bval = ov;
+      }
+    }
+    const double sgn = bval < 0 ? -1.0 : 1.0;
+    for (int row = lane; row < d.n1; row += 64) {
+      const double x = sgn * ucol(row);
+      U[int64_t(row) * k + i] = T(x);
+      Us[int64_t(row) * k + i] = T(T(x) * T(sg));
+    }
+    if (V != nullptr)
+      for (int row = lane; row < d.n2; row += 64) Vo[int64_t(row) * k + i] = T(sgn * vcol(row));
+    if (lane == 0) shat[int64_t(slice) * k + i] = T(sg);
+  }
+}
+
+// General kernel: W and V in the workspace.  RPL: rows per lane (mr <= 64 * RPL).
 template <typename T, int RPL>
-__global__ __launch_bounds__(kJacobiThreads) void jacobi_kernel(
+__global__ __launch_bounds__(kJacobiThreads) void jacobi_global_kernel(
     const T* __restrict__ ah, T* __restrict__ wbuf, T* __restrict__ vbuf, SvdDims d,
     int max_sweeps, T* __restrict__ uhat, T* __restrict__ shat, T* __restrict__ vhat,
     T* __restrict__ us, int32_t* __restrict__ info) {
@@ -141,18 +271,14 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_kernel(
           be = wave_sum(be);
           ga = wave_sum(ga);
           if (!live[b]) continue;
-          if (!(isfinite(al) && isfinite(be) && isfinite(ga))) {
+          double c, s;
+          const int flag = rotation(al, be, ga, tol, c, s);
+          if (flag == 2) {
             if (lane == 0) s_bad = 1;
             continue;
           }
-          if (!(fabs(ga) > tol * sqrt(al * be))) continue;
+          if (flag == 0) continue;
           ++my_rot;
-          // Rotation that zeroes the (i, j) inner product (Rutishauser's form).
-          const double zeta = (be - al) / (2.0 * ga);
-          const double t = fabs(zeta) > 1e150 ? 0.5 / zeta
-                                              : copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t);
-          const double s = c * t;
 #pragma unroll
           for (int tt = 0; tt < RPL; ++tt) {
             const int row = lane + 64 * tt;
@@ -184,86 +310,326 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_kernel(
     }
   }
 
-  // ---- singular values, ordering ----------------------------------------------
-  for (int c = wave; c < nc; c += kJacobiWaves) {
-    double acc = 0;
-    for (int row = lane; row < mr; row += 64) {
-      const double x = double(W[int64_t(c) * mr + row]);
-      acc = fma(x, x, acc);
+  emit_factors<T>(W, V, d, slice, uhat, shat, vhat, us, s_sigma, s_order);
+  if (threadIdx.x == 0) info[slice] = (converged && s_bad == 0) ? sweeps : -sweeps;
+}
+
+// DPP move of a 64-bit value within rows of 16 lanes (CTRL: DPP control word).
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 16 lanes of a DPP row.  Every step adds a value and its partner
+// (rotate by 8 and by 4 within the row, then swap pairs of 2 and of 1 within
+// quads), and each partial is formed as a + b in one lane and b + a in the
+// other, so all 16 lanes end with the same bits.
+__device__ __forceinline__ double row_sum16(double x) {
+  x += dpp64<0x128>(x);  // row_ror:8
+  x += dpp64<0x124>(x);  // row_ror:4
+  x += dpp64<0x4e>(x);   // quad_perm [2,3,0,1]
+  x += dpp64<0xb1>(x);   // quad_perm [1,0,3,2]
+  return x;
+}
+
+// Per-lane partial of the three dot products over the RPL rows a lane holds.
+// FP64 data accumulates in FP64.  FP32 data accumulates its (at most 16)
+// terms in FP32 and the partials are summed across the row in FP64, so the
+// error of gamma relative to |w_i||w_j| stays near 2^-24, below the rotation
+// threshold sqrt(mr) 2^-24.
+template <typename T, int RPL>
+__device__ __forceinline__ void lane_dots(const T (&x)[RPL], const T (&y)[RPL], double& al,
+                                          double& be, double& ga) {
+  if constexpr (sizeof(T) == 8) {
+    al = be = ga = 0;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      al = fma(x[t], x[t], al);
+      be = fma(y[t], y[t], be);
+      ga = fma(x[t], y[t], ga);
     }
-    acc = wave_sum(acc);
-    if (lane == 0) s_sigma[c] = sqrt(acc);
-  }
-  __syncthreads();
-  // Rank by a strict total order: larger sigma first, NaN after every number,
-  // ties (and NaNs) by column index; the ranks are therefore a permutation.
-  for (int c = threadIdx.x; c < nc; c += kJacobiThreads) {
-    const double sc = s_sigma[c];
-    const bool nan_c = sc != sc;
-    int rank = 0;
-    for (int o = 0; o < nc; ++o) {
-      const double so = s_sigma[o];
-      const bool nan_o = so != so;
-      const bool before = nan_o ? (nan_c && o < c)
-                                : (nan_c || so > sc || (so == sc && o < c));
-      rank += before;
+  } else {
+    float a = 0.f, b = 0.f, g = 0.f;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      a = fmaf(x[t], x[t], a);
+      b = fmaf(y[t], y[t], b);
+      g = fmaf(x[t], y[t], g);
     }
-    s_order[rank] = c;
+    al = a;
+    be = b;
+    ga = g;
   }
+}
+
+constexpr int kUnits = 4 * kJacobiWaves;  // 16-lane rows per workgroup
+
+// Register-resident Jacobi on W only.  A unit is one 16-lane DPP row; column
+// entries are spread over its lanes, RPL rows per lane (row = lane16 + 16 t,
+// mr <= 16 * RPL).  Each unit owns J consecutive tournament slots and works on
+// one of its pairs at a time, so a wavefront rotates four pairs at once.
+// nunits * J slots in total, NP = 2 * nunits * J positions (positions beyond
+// nc hold zero columns, which never rotate).
+template <typename T, int J, int RPL>
+__global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
+    const T* __restrict__ ah, T* __restrict__ wbuf, SvdDims d, int nunits, int max_sweeps,
+    T* __restrict__ uhat, T* __restrict__ shat, T* __restrict__ vhat, T* __restrict__ us,
+    int32_t* __restrict__ info) {
+  const int slice = blockIdx.x;
+  const int lane16 = threadIdx.x & 15;
+  const int unit = threadIdx.x >> 4;
+  const int mr = d.mr, nc = d.nc;
+  const int H = nunits * J;
+  const int CIRC = 2 * H - 1;            // positions 1..NP-1 form the circle
+  const bool active = unit < nunits;
+  const int q0 = unit * J;               // first slot of this unit
+  const T* a = ah + int64_t(slice) * d.n1 * d.n2;
+  T* W = wbuf + int64_t(slice) * nc * mr;
+
+  __shared__ T s_x[2][2][kUnits][16 * RPL];  // [round parity][top, bottom][unit][row]
+  __shared__ int s_rot;
+  __shared__ int s_bad;
+  __shared__ double s_sigma[1024];
+  __shared__ int s_order[1024];
+
+  // Column held by slot q in round r (0 <= r < CIRC): the circle advances one
+  // position per round and position p initially holds column p.
+  // (0 <= q-1, 2H-2-q < CIRC and 0 <= r < CIRC, so one conditional wrap suffices.)
+  auto wrap = [&](int x) { return (x < 0 ? x + CIRC : x) + 1; };
+  auto top_id = [&](int q, int r) { return q == 0 ? 0 : wrap(q - 1 - r); };
+  auto bot_id = [&](int q, int r) { return wrap(2 * H - 2 - q - r); };
+  auto w_src = [&](int row, int c) -> T {
+    return d.trans ? a[c * d.n2 + row] : a[row * d.n2 + c];
+  };
+
+  T top[J][RPL], bot[J][RPL];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int it = top_id(q0 + j, 0), ib = bot_id(q0 + j, 0);
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int row = lane16 + 16 * t;
+      const bool ok = active && row < mr;
+      top[j][t] = (ok && it < nc) ? w_src(row, it) : T(0);
+      bot[j][t] = (ok && ib < nc) ? w_src(row, ib) : T(0);
+    }
+  }
+  if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
 
-  // ---- outputs: k leading triplets ----------------------------------------------
-  // U column i has n1 entries, V column i has n2 entries.  Without transposition
-  // U = W_c / sigma (mr = n1 rows) and V = V_c (nc = n2 rows); with it the roles swap.
+  const double tol = sqrt(double(mr)) * Unit<T>::value;
+  int sweeps = 0;
+  bool converged = false;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    if (threadIdx.x == 0) s_rot = 0;
+    __syncthreads();
+    int my_rot = 0;
+    bool my_bad = false;
+    for (int r = 0; r < CIRC; ++r) {
+      if (active) {
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          double al, be, ga;
+          lane_dots<T, RPL>(top[j], bot[j], al, be, ga);
+          al = row_sum16(al);
+          be = row_sum16(be);
+          ga = row_sum16(ga);
+          double cd, sd;
+          const int flag = rotation(al, be, ga, tol, cd, sd);
+          my_bad |= flag == 2;
+          if (flag == 1) {
+            const T c = T(cd), sn = T(sd);
+            ++my_rot;
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+              const T x = top[j][t], y = bot[j][t];
+              top[j][t] = c * x - sn * y;
+              bot[j][t] = sn * x + c * y;
+            }
+          }
+        }
+        // Boundary columns for the neighbouring units.
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          s_x[r & 1][0][unit][lane16 + 16 * t] = top[J - 1][t];
+          s_x[r & 1][1][unit][lane16 + 16 * t] = bot[0][t];
+        }
+      }
+      __syncthreads();
+      if (active) {
+        // Advance the circle by one position: top[q] -> top[q+1], top[H-1] ->
+        // bottom[H-1], bottom[q] -> bottom[q-1], bottom[0] -> top[1]; top[0] stays.
+        const int q1 = q0 + J - 1;
+        T first[RPL], last[RPL];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int row = lane16 + 16 * t;
+          first[t] = q0 == 0 ? top[0][t]
+                             : (q0 == 1 ? s_x[r & 1][1][0][row] : s_x[r & 1][0][unit - 1][row]);
+          // (with a single slot, top[0] is the fixed position and nothing moves)
+          last[t] = q1 == H - 1 ? (H == 1 ? bot[J - 1][t] : top[J - 1][t])
+                                : s_x[r & 1][1][unit + 1][row];
+        }
+#pragma unroll
+        for (int j = J - 1; j >= 1; --j)
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) top[j][t] = (q0 + j == 1) ? bot[0][t] : top[j - 1][t];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) top[0][t] = first[t];
+#pragma unroll
+        for (int j = 0; j < J - 1; ++j)
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) bot[j][t] = bot[j + 1][t];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) bot[J - 1][t] = last[t];
+      }
+    }
+    // One count per unit (all 16 lanes of a unit took the same decisions).
+    if (active && lane16 == 0 && my_rot) atomicAdd(&s_rot, my_rot);
+    if (active && lane16 == 0 && my_bad) s_bad = 1;
+    __syncthreads();
+    sweeps = sw + 1;
+    const bool done = (s_rot == 0);
+    const bool bad = (s_bad != 0);
+    __syncthreads();
+    if (bad) break;
+    if (done) {
+      converged = true;
+      break;
+    }
+  }
+
+  if (active) {
+    // W back to the workspace (after whole sweeps every slot holds its initial
+    // columns again).
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int it = top_id(q0 + j, 0), ib = bot_id(q0 + j, 0);
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int row = lane16 + 16 * t;
+        if (row < mr) {
+          if (it < nc) W[it * mr + row] = top[j][t];
+          if (ib < nc) W[ib * mr + row] = bot[j][t];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  emit_factors<T>(W, static_cast<const T*>(nullptr), d, slice, uhat, shat, vhat, us, s_sigma,
+                  s_order);
+  if (threadIdx.x == 0) info[slice] = (converged && s_bad == 0) ? sweeps : -sweeps;
+}
+
+// The factor the register-resident kernel did not form, from A V = U Sigma:
+// vhat_i = A^T u_i / sigma_i (n1 >= n2), or u_i = A vhat_i / sigma_i (n1 < n2),
+// accumulated in FP64 from the coefficients.  In the second case the sign
+// convention (largest |U| entry positive) is applied here to both columns,
+// and U * sigma is written for the rebuild.  One workgroup per (slice, i);
+// columns with sigma_i = 0 come out zero.
+template <typename T>
+__global__ __launch_bounds__(256) void recover_kernel(const T* __restrict__ ah, SvdDims d,
+                                                      T* __restrict__ uhat,
+                                                      const T* __restrict__ shat,
+                                                      T* __restrict__ vhat, T* __restrict__ us) {
   const int k = d.k;
+  const int slice = blockIdx.x / k;
+  const int i = blockIdx.x % k;
+  const int mr = d.mr, nc = d.nc;
+  const T* A = ah + int64_t(slice) * d.n1 * d.n2;
   T* U = uhat + int64_t(slice) * d.n1 * k;
   T* Vo = vhat + int64_t(slice) * d.n2 * k;
-  T* Us = us + int64_t(slice) * d.n1 * k;
-  for (int i = wave; i < k; i += kJacobiWaves) {
-    const int c = s_order[i];
-    const double sg = s_sigma[c];
-    const double inv = sg > 0 ? 1.0 / sg : 0.0;
-    // Values of the final U column: either W_c * inv or V_c.
-    auto ucol = [&](int row) -> double {
-      return d.trans ? double(V[int64_t(c) * nc + row]) : double(W[int64_t(c) * mr + row]) * inv;
-    };
-    auto vcol = [&](int row) -> double {
-      return d.trans ? double(W[int64_t(c) * mr + row]) * inv : double(V[int64_t(c) * nc + row]);
-    };
-    // Largest |U| entry, lowest row on ties.
-    double best = -1.0;
-    int brow = 0x7fffffff;
-    double bval = 0;
-    for (int row = lane; row < d.n1; row += 64) {
-      const double x = ucol(row);
-      const double ax = fabs(x);
-      if (ax > best) {
-        best = ax;
-        brow = row;
-        bval = x;
-      }
-    }
+  const T* src = d.trans ? Vo : U;  // the column formed from W, mr entries
+  T* dst = d.trans ? U : Vo;        // the column recovered here, nc entries
+  __shared__ double s_src[1024];
+  __shared__ double s_best[256];
+  __shared__ int s_row[256];
+  __shared__ double s_val[256];
+  const double sg = double(shat[int64_t(slice) * k + i]);
+  const double inv = sg > 0 ? 1.0 / sg : 0.0;
+  for (int t = threadIdx.x; t < mr; t += 256) s_src[t] = double(src[int64_t(t) * k + i]);
+  __syncthreads();
+  double out[4];
+  double best = -1.0, bval = 0.0;
+  int brow = 0x7fffffff;
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      const double ob = __shfl_xor(best, o, 64);
-      const int orow = __shfl_xor(brow, o, 64);
-      const double ov = __shfl_xor(bval, o, 64);
-      if (ob > best || (ob == best && orow < brow)) {
-        best = ob;
-        brow = orow;
-        bval = ov;
+  for (int j = 0; j < 4; ++j) {
+    const int r = threadIdx.x + 256 * j;
+    double acc = 0;
+    if (r < nc) {
+      if (d.trans)
+        for (int t = 0; t < mr; ++t) acc = fma(double(A[int64_t(r) * d.n2 + t]), s_src[t], acc);
+      else
+        for (int t = 0; t < mr; ++t) acc = fma(double(A[int64_t(t) * d.n2 + r]), s_src[t], acc);
+      acc *= inv;
+      if (fabs(acc) > best) {
+        best = fabs(acc);
+        brow = r;
+        bval = acc;
       }
     }
-    const double sgn = bval < 0 ? -1.0 : 1.0;
-    for (int row = lane; row < d.n1; row += 64) {
-      const double x = sgn * ucol(row);
-      U[int64_t(row) * k + i] = T(x);
-      Us[int64_t(row) * k + i] = T(T(x) * T(sg));
-    }
-    for (int row = lane; row < d.n2; row += 64) Vo[int64_t(row) * k + i] = T(sgn * vcol(row));
-    if (lane == 0) shat[int64_t(slice) * k + i] = T(sg);
+    out[j] = acc;
   }
-  if (threadIdx.x == 0) info[slice] = (converged && s_bad == 0) ? sweeps : -sweeps;
+  double sgn = 1.0;
+  if (d.trans) {
+    // Largest |U| entry over the column, lowest row on ties.
+    s_best[threadIdx.x] = best;
+    s_row[threadIdx.x] = brow;
+    s_val[threadIdx.x] = bval;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) {
+        const int o = threadIdx.x + w;
+        if (s_best[o] > s_best[threadIdx.x] ||
+            (s_best[o] == s_best[threadIdx.x] && s_row[o] < s_row[threadIdx.x])) {
+          s_best[threadIdx.x] = s_best[o];
+          s_row[threadIdx.x] = s_row[o];
+          s_val[threadIdx.x] = s_val[o];
+        }
+      }
+      __syncthreads();
+    }
+    sgn = s_val[0] < 0 ? -1.0 : 1.0;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int r = threadIdx.x + 256 * j;
+    if (r < nc) {
+      const T x = T(sgn * out[j]);
+      dst[int64_t(r) * k + i] = x;
+      if (d.trans) us[int64_t(slice) * d.n1 * k + int64_t(r) * k + i] = T(x * T(sg));
+    }
+  }
+  if (d.trans && sgn < 0)
+    for (int t = threadIdx.x; t < mr; t += 256) Vo[int64_t(t) * k + i] = T(-s_src[t]);
+}
+
+// One Newton-Schulz step of the polar iteration, X <- X (3I - X^T X) / 2,
+// for the recovered factor X (one slice (n, k) row-major per workgroup): the
+// recovery inherits the error of U amplified by sigma_1 / sigma_i, and this
+// step removes its non-orthogonality to second order.  FP64 Gram, k <= 64.
+template <typename T>
+__global__ __launch_bounds__(256) void polish_kernel(T* __restrict__ x, int n, int k) {
+  __shared__ double s_e[64 * 64];
+  T* X = x + int64_t(blockIdx.x) * n * k;
+  for (int e = threadIdx.x; e < k * k; e += 256) {
+    const int a = e / k, b = e % k;
+    double acc = 0;
+    for (int r = 0; r < n; ++r) acc = fma(double(X[int64_t(r) * k + a]), double(X[int64_t(r) * k + b]), acc);
+    s_e[e] = acc - (a == b ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < n; r += 256) {
+    double row[64];
+    for (int i = 0; i < k; ++i) row[i] = double(X[int64_t(r) * k + i]);
+    for (int i = 0; i < k; ++i) {
+      double acc = 0;
+      for (int j = 0; j < k; ++j) acc = fma(row[j], s_e[j * k + i], acc);
+      X[int64_t(r) * k + i] = T(row[i] - 0.5 * acc);
+    }
+  }
 }
 
 // max |X^T X - I| over the k x k Gram matrix of one slice of X (n x k, row-major), FP64.
@@ -373,16 +739,43 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
 
   const dim3 grid{unsigned(p)};
   const dim3 block{unsigned(kJacobiThreads)};
-  if (d.mr <= 64)
-    hipLaunchKernelGGL((jacobi_kernel<T, 1>), grid, block, 0, s, ah, w, v, d, max_sweeps, uhat, shat, vhat, us, info);
-  else if (d.mr <= 128)
-    hipLaunchKernelGGL((jacobi_kernel<T, 2>), grid, block, 0, s, ah, w, v, d, max_sweeps, uhat, shat, vhat, us, info);
-  else if (d.mr <= 256)
-    hipLaunchKernelGGL((jacobi_kernel<T, 4>), grid, block, 0, s, ah, w, v, d, max_sweeps, uhat, shat, vhat, us, info);
-  else if (d.mr <= 512)
-    hipLaunchKernelGGL((jacobi_kernel<T, 8>), grid, block, 0, s, ah, w, v, d, max_sweeps, uhat, shat, vhat, us, info);
-  else
-    hipLaunchKernelGGL((jacobi_kernel<T, 16>), grid, block, 0, s, ah, w, v, d, max_sweeps, uhat, shat, vhat, us, info);
+  // Register-resident kernel when the columns fit: each of up to 32 units
+  // (16-lane rows) owns J slots, J the smallest power of two with
+  // 32 * J >= nc_pad / 2; RPL = rows per lane.
+  const int half = d.ncp / 2;
+  int J = 1;
+  while (J * kUnits < half) J *= 2;
+  const int nunits = (half + J - 1) / J;
+  int rpl = 1;
+  while (rpl * 16 < d.mr) rpl *= 2;
+  const bool reg_ok = rpl <= 16 && J <= 4 && (sizeof(T) == 4 || (rpl <= 8 && J * rpl <= 16));
+  if (reg_ok) {
+#define WP_JREG(JJ, RR)                                                                        \
+  if (J == JJ && rpl == RR)                                                                    \
+    hipLaunchKernelGGL((jacobi_reg_kernel<T, JJ, RR>), grid, block, 0, s, ah, w, d, nunits,     \
+                       max_sweeps, uhat, shat, vhat, us, info);
+    WP_JREG(1, 1) WP_JREG(1, 2) WP_JREG(1, 4) WP_JREG(1, 8)
+    WP_JREG(2, 1) WP_JREG(2, 2) WP_JREG(2, 4) WP_JREG(2, 8)
+    WP_JREG(4, 1) WP_JREG(4, 2) WP_JREG(4, 4)
+    if constexpr (sizeof(T) == 4) {
+      WP_JREG(1, 16) WP_JREG(2, 16) WP_JREG(4, 8) WP_JREG(4, 16)
+    }
+#undef WP_JREG
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((recover_kernel<T>), dim3(unsigned(p * k)), dim3(256), 0, s, ah, d, uhat,
+                       shat, vhat, us);
+  } else if (d.mr <= 64) {
+    hipLaunchKernelGGL((jacobi_global_kernel<T, 1>), grid, block, 0, s, ah, w, v, d, max_sweeps, uhat, shat, vhat, us, info);
+  } else if (d.mr <= 128) {
+    hipLaunchKernelGGL((jacobi_global_kernel<T, 2>), grid, block, 0, s, ah, w, v, d, max_sweeps, uhat, shat, vhat, us, info);
+  } else if (d.mr <= 256) {
+    hipLaunchKernelGGL((jacobi_global_kernel<T, 4>), grid, block, 0, s, ah, w, v, d, max_sweeps, uhat, shat, vhat, us, info);
+  } else if (d.mr <= 512) {
+    hipLaunchKernelGGL((jacobi_global_kernel<T, 8>), grid, block, 0, s, ah, w, v, d, max_sweeps, uhat, shat, vhat, us, info);
+  } else {
+    hipLaunchKernelGGL((jacobi_global_kernel<T, 16>), grid, block, 0, s, ah, w, v, d, max_sweeps, uhat, shat, vhat, us, info);
+  }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
 
@@ -402,6 +795,18 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
         e = launch_lift_f32(LiftKind::kInverse, reinterpret_cast<const float*>(ah),
                             reinterpret_cast<float*>(ak), n1 * n2, p, L, s);
     }
+    if (e != hipSuccess) return e;
+  }
+
+  if (reg_ok && k <= 64) {
+    // Orthonormalise the recovered factor (after the rebuild, which uses the
+    // recovered columns as they are: their product with U is the exact rank-k
+    // projection U U^T A).
+    if (d.trans)
+      hipLaunchKernelGGL((polish_kernel<T>), dim3(unsigned(p)), dim3(256), 0, s, uhat, int(n1), k);
+    else
+      hipLaunchKernelGGL((polish_kernel<T>), dim3(unsigned(p)), dim3(256), 0, s, vhat, int(n2), k);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
 

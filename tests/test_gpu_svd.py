@@ -43,11 +43,14 @@ def test_config1_f64_full_rank(wp):
     _check_factors(res, orc.lift_fwd(a, 2), 24, 1e-12)
 
 
+# Register-resident kernel: both orientations (n1 < n2 runs on the transpose),
+# odd column counts (a zero tournament column), 1 and 2 columns, rows spanning
+# several lanes.  General kernel: more than 256 rows.
 @pytest.mark.parametrize("shape,k", [((8, 10, 20), 5), ((16, 21, 13), 7), ((4, 9, 9), 9),
-                                     ((8, 65, 40), 3), ((2, 3, 70), 1), ((32, 7, 7), 4)])
+                                     ((8, 65, 40), 3), ((2, 3, 70), 1), ((32, 7, 7), 4),
+                                     ((4, 5, 1), 1), ((4, 2, 6), 2), ((8, 130, 100), 10),
+                                     ((4, 300, 40), 6), ((2, 24, 520), 5)])
 def test_f64_shapes(wp, shape, k):
-    # Both orientations (n1 < n2 runs on the transpose), odd column counts (a
-    # dummy tournament column) and rows spanning several lanes.
     import torch
     p, n1, n2 = shape
     L = 2 if p % 4 == 0 else 1
@@ -102,3 +105,20 @@ def test_nonfinite_input_terminates(wp):
     # slice 1 is mixed into coefficient slices 0 (s_1) and 2 (d_1)
     assert info[0] < 0 and info[2] < 0
     assert info[1] > 0 and info[3] > 0
+
+
+@pytest.mark.parametrize("shape,k", [((16, 100, 60), 10), ((8, 33, 64), 8), ((4, 256, 256), 20)])
+def test_f32_shapes(wp, shape, k):
+    import torch
+    p, n1, n2 = shape
+    L = 2
+    a = cast(np.random.default_rng(n1 + n2).standard_normal(shape), np.float32)
+    res = wp.w_svd(to_dev(a, torch.float32), L, k)
+    torch.cuda.synchronize()
+    assert host(res.info).min() > 0
+    _, sh_ref, _, ak_ref = orc.w_svd(a, L, k)
+    assert rel_fro(host(res.shat), sh_ref) <= 1e-5
+    # Gaussian slices have well separated leading singular values: the rank-k
+    # approximation is determined to about the FP32 rounding of the data.
+    assert rel_fro(host(res.ak), ak_ref) <= 1e-4
+    assert host(res.orth_err).max() <= 1e-4
