@@ -203,16 +203,31 @@ def main():
                           "unit": "TFLOP/s", "frac": round(ach / peak, 4),
                           "launches_per_step": launches, "ms_per_launch": round(per_launch_ms, 4),
                           "algorithmic_flops_per_launch": flops}
-    # dominant kernel of the w-product part (the w-svd call is several kernels)
+    # The Jacobi kernel dominates the step.  Its algorithmic work per pair visit
+    # is 6*mr flops of dot products plus 6*mr of rotation; a sweep visits
+    # nc(nc-1)/2 pairs; the sweeps are those the slices actually ran.  The
+    # duration is the event-timed w_svd call (the Jacobi kernel plus the
+    # lifting, recovery, rebuild and orthogonality kernels around it).
+    sweeps_total = int(np.abs(info).sum())
+    jac_flops = 12.0 * SVD_N * (SVD_N * (SVD_N - 1) / 2) * sweeps_total
+    jac_ach = jac_flops / (kern_ms["w_svd"] * 1e-3) / 1e12
+    rows["w_svd"] = {"bound": "alu", "achieved": round(jac_ach, 2), "peak": FP32_PEAK_TFS,
+                     "unit": "TFLOP/s", "frac": round(jac_ach / FP32_PEAK_TFS, 4),
+                     "launches_per_step": 1, "ms_per_launch": round(kern_ms["w_svd"], 4),
+                     "algorithmic_flops_per_launch": jac_flops,
+                     "note": "Jacobi kernel: 12*mr flops per pair visit, FP32 rotations and "
+                             "partial dots, FP64 sums and angles; duration = whole w_svd call"}
+    traffic = measured_traffic()
+    for name, row in rows.items():
+        row["traffic"] = traffic.get(name)
     dom_name = max(rows, key=lambda k: kern_ms[k])
     roof = dict(rows[dom_name])
-    roof["kernel"] = dom_name
-    roof["traffic"] = None
+    roof["kernel"] = "jacobi_reg_kernel<float,4,16> (w_svd)" if dom_name == "w_svd" else dom_name
 
     # ---- CPU baseline: the oracle on a bounded sample of the same workload ----
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(torch, a, b, g, c_x3, da_x3)
+        cpu = cpu_baseline(torch, a, b, g, c_x3, da_x3, x_hsi, res)
 
     line = {
         "metric": "w-product fwd+bwd effective TFLOP/s (bf16x3 face-products, 512x512x256, L=4)",
@@ -250,18 +265,49 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(torch, a, b, g, c_gpu, da_gpu):
-    """Oracle w-product fwd+bwd on rows [0, 64) of A (1/8 of the work), timed on host cores."""
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary.
+
+    FETCH_SIZE and WRITE_SIZE were taken in two runs of this benchmark and
+    scaled by the counters of a plain copy; a kernel's figure is used only while
+    its source file still has the hash recorded with it, otherwise None.
+    """
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic_bench_step.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        rec = json.load(f)
+    out = {}
+    for name, k in rec.get("kernels", {}).items():
+        src = os.path.join(ROOT, k["source"])
+        if os.path.exists(src):
+            with open(src, "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() == k["source_sha256"]:
+                    out[name] = k["traffic_bytes"]
+    return out
+
+
+def cpu_baseline(torch, a, b, g, c_gpu, da_gpu, x_hsi, svd_res):
+    """The FP64 oracle on the step's work, timed on the host cores.
+
+    w-product forward + backward of the whole 512x512x256 pair (the metric's
+    unit), then the w-svd of the same hyperspectral-like tensor.
+    """
     import oracle
-    rows = 64
+    rows = N1
     a_s = a[:, :rows, :].double().cpu().numpy()
     b_h = b.double().cpu().numpy()
     g_s = g[:, :rows, :].double().cpu().numpy()
     t0 = time.perf_counter()
     c_ref = oracle.w_product(a_s, b_h, LEV)
-    da_ref, _db_part = oracle.w_product_vjp(a_s, b_h, g_s, LEV)
+    da_ref, _db = oracle.w_product_vjp(a_s, b_h, g_s, LEV)
     t1 = time.perf_counter()
     sample_flops = 3.0 * 2.0 * rows * N2 * N3 * P
+    x_h = x_hsi.double().cpu().numpy()
+    t2 = time.perf_counter()
+    _, sh_ref, _, ak_ref = oracle.w_svd(x_h, SVD_L, SVD_K)
+    t3 = time.perf_counter()
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
@@ -276,12 +322,16 @@ def cpu_baseline(torch, a, b, g, c_gpu, da_gpu):
         "unit": "TFLOP/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": "FP64 NumPy oracle, w-product fwd+bwd of rows 0..63 of A (64x512 by 512x512, "
-                  "256 slices, L=4): 1/8 of the step's w-product work; %.1f s" % (t1 - t0),
+        "sample": "FP64 NumPy oracle: the step's whole w-product fwd+bwd (512x512x256 pair, "
+                  "L=4) in %.1f s; w-svd of the 256x256x192 tensor in %.1f s"
+                  % (t1 - t0, t3 - t2),
         "seconds": round(t1 - t0, 3),
-        "rel_err_gpu_bf16x3_vs_oracle": {
-            "C_rows0_63": rel(c_gpu[:, :rows, :].double().cpu().numpy(), c_ref),
-            "dA_rows0_63": rel(da_gpu[:, :rows, :].double().cpu().numpy(), da_ref),
+        "w_svd_seconds": round(t3 - t2, 3),
+        "rel_err_gpu_vs_oracle": {
+            "C_bf16x3": rel(c_gpu.double().cpu().numpy(), c_ref),
+            "dA_bf16x3": rel(da_gpu.double().cpu().numpy(), da_ref),
+            "w_svd_shat": rel(svd_res.shat.double().cpu().numpy(), sh_ref),
+            "w_svd_Ak": rel(svd_res.ak.double().cpu().numpy(), ak_ref),
         },
     }
 
