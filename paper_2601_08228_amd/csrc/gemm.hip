@@ -7,14 +7,15 @@
 //   BF16  : v_mfma_f32_32x32x16_bf16, 256 x 256 workgroup tile, BK = 32, with
 //           the split-precision variant hi*hi + hi*lo + lo*hi accumulated in
 //           FP32 (the lo*lo term is dropped).
-// A workgroup is 4 wavefronts in a 2 x 2 grid.  Operand tiles are staged in LDS
+// A workgroup is a WM x WN grid of wavefronts (2 x 2; 2 x 4 for BF16, two per SIMD).  Operand tiles are staged in LDS
 // with K contiguous inside each row, so every lane fetches one 16-byte chunk of
 // consecutive-K values per fragment read (one ds_read_b128).  Rows are 64 B
 // (4 chunks) and chunk c of row r is stored at chunk c ^ ((r >> 1) & 3), which
 // makes the 16-byte reads of 8 consecutive rows hit disjoint banks.  Operands
 // stored with K as the slow dimension (A transposed, B not transposed) are
-// transposed in registers on their way to LDS: a thread loads a CH x CH
-// micro-block with CH 16-byte loads and writes CH 16-byte LDS chunks.
+// transposed in registers on their way to LDS: a thread loads a CH x RW
+// micro-block (RW = CH, or 4 for bf16) with CH loads and writes RW 16-byte
+// LDS chunks.
 //
 // Pipeline: two LDS stages; the global loads of tile t+1 are issued into
 // registers before the MFMAs of tile t and written to the other stage after
@@ -34,9 +35,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
-constexpr int kWaves = 4;
-constexpr int kThreads = 64 * kWaves;
 constexpr int kChunksPerRow = 4;  // 64-byte LDS rows
 constexpr int kNumXcd = 8;
 
@@ -49,6 +49,8 @@ struct CfgF64 {
   static constexpr int G = 4;      // lane groups per MFMA (64 / TM)
   static constexpr int MT = 2;     // MFMA tiles per wave along M
   static constexpr int NT = 2;     // MFMA tiles per wave along N
+  static constexpr int WM = 2;     // wavefronts along M
+  static constexpr int WN = 2;     // wavefronts along N
   static constexpr int ACC_REGS = 4;
   static constexpr bool kSplit = false;
 };
@@ -62,6 +64,8 @@ struct CfgF32 {
   static constexpr int G = 2;
   static constexpr int MT = 2;
   static constexpr int NT = 2;
+  static constexpr int WM = 2;
+  static constexpr int WN = 2;
   static constexpr int ACC_REGS = 16;
   static constexpr bool kSplit = false;
 };
@@ -74,7 +78,9 @@ struct CfgBF16 {
   static constexpr int TM = 32;
   static constexpr int G = 2;
   static constexpr int MT = 4;
-  static constexpr int NT = 4;
+  static constexpr int NT = 2;
+  static constexpr int WM = 2;     // 8 wavefronts, two per SIMD: one computes while
+  static constexpr int WN = 4;     // the other waits on memory
   static constexpr int ACC_REGS = 16;
   static constexpr bool kSplit = true;
 };
@@ -82,8 +88,9 @@ struct CfgBF16 {
 template <class Cfg>
 struct Dims {
   static constexpr int BK = Cfg::CH * kChunksPerRow;        // K per LDS stage
-  static constexpr int BM = 2 * Cfg::MT * Cfg::TM;           // 2 waves along M
-  static constexpr int BN = 2 * Cfg::NT * Cfg::TM;           // 2 waves along N
+  static constexpr int THREADS = 64 * Cfg::WM * Cfg::WN;
+  static constexpr int BM = Cfg::WM * Cfg::MT * Cfg::TM;
+  static constexpr int BN = Cfg::WN * Cfg::NT * Cfg::TM;
   static constexpr int KG = kChunksPerRow / Cfg::G;          // k-groups per stage
   static constexpr int ROW_BYTES = 16 * kChunksPerRow;
   static constexpr int A_BYTES = BM * ROW_BYTES;
@@ -131,18 +138,22 @@ __device__ __forceinline__ void mma_bf16(const u32x4& a, const u32x4& b, f32x16&
 // (M or N) by BK columns of K.  K_CONTIG: the stored matrix has K contiguous
 // (row pitch ld along R); otherwise R is contiguous and the pitch ld runs
 // along K.  The work items of all planes are dealt over the whole workgroup.
-template <class Cfg, int R, bool K_CONTIG, int NPL>
+template <class Cfg, int R, bool K_CONTIG, int NPL, int kThreads>
 struct TileLoader {
   using In = typename Cfg::In;
   static constexpr int CH = Cfg::CH;
   static constexpr int BK = CH * kChunksPerRow;
+  // Transposed staging: micro-blocks of CH K-rows by RW R-columns (RW = 4 for
+  // bf16, i.e. 8-byte loads, to keep the staged block at 16 registers).
+  static constexpr int RW = CH == 8 ? 4 : CH;
+  static constexpr int LB = RW * int(sizeof(In));  // bytes per transposed-path load
   // Work items per plane: K-contiguous -> one chunk each; otherwise one
-  // CH x CH micro-block each.
-  static constexpr int ITEMS = K_CONTIG ? R * kChunksPerRow : (BK / CH) * (R / CH);
+  // CH x RW micro-block each.
+  static constexpr int ITEMS = K_CONTIG ? R * kChunksPerRow : (BK / CH) * (R / RW);
   static constexpr int TOTAL = ITEMS * NPL;
   static constexpr int PER_THREAD = (TOTAL + kThreads - 1) / kThreads;
-  static constexpr int REGS = K_CONTIG ? 1 : CH;  // 16-byte chunks per item
-  u32x4 buf[PER_THREAD][REGS];
+  static constexpr int WORDS = K_CONTIG ? 4 : CH * LB / 4;  // 32-bit words per item
+  unsigned int buf[PER_THREAD][WORDS];
 
   // Load element (r, k) of the tile with bounds checks (zero outside).
   __device__ __forceinline__ static In elem(const In* base, int64_t ld, int r, int k, int rlim,
@@ -167,7 +178,8 @@ struct TileLoader {
         const int c = item % kChunksPerRow;
         const int k0 = c * CH;
         if (vec_ok && r < rlim && k0 + CH <= klim) {
-          buf[i][0] = *reinterpret_cast<const u32x4*>(b + int64_t(r) * ld + k0);
+          const u32x4 v = *reinterpret_cast<const u32x4*>(b + int64_t(r) * ld + k0);
+          __builtin_memcpy(&buf[i][0], &v, 16);
         } else {
           In tmp[CH];
 #pragma unroll
@@ -175,21 +187,28 @@ struct TileLoader {
           __builtin_memcpy(&buf[i][0], tmp, 16);
         }
       } else {
-        constexpr int RB = R / CH;  // micro-blocks along R
+        constexpr int RB = R / RW;  // micro-blocks along R
         const int kb = item / RB;
         const int rb = item % RB;
         const int k0 = kb * CH;
-        const int r0 = rb * CH;
+        const int r0 = rb * RW;
 #pragma unroll
         for (int e = 0; e < CH; ++e) {
           const int k = k0 + e;
-          if (vec_ok && k < klim && r0 + CH <= rlim) {
-            buf[i][e] = *reinterpret_cast<const u32x4*>(b + int64_t(k) * ld + r0);
+          unsigned int* dst = &buf[i][e * (LB / 4)];
+          if (vec_ok && k < klim && r0 + RW <= rlim) {
+            if constexpr (LB == 16) {
+              const u32x4 v = *reinterpret_cast<const u32x4*>(b + int64_t(k) * ld + r0);
+              __builtin_memcpy(dst, &v, 16);
+            } else {
+              const u32x2 v = *reinterpret_cast<const u32x2*>(b + int64_t(k) * ld + r0);
+              __builtin_memcpy(dst, &v, 8);
+            }
           } else {
-            In tmp[CH];
+            In tmp[RW];
 #pragma unroll
-            for (int f = 0; f < CH; ++f) tmp[f] = elem(b, ld, r0 + f, k, rlim, klim);
-            __builtin_memcpy(&buf[i][e], tmp, 16);
+            for (int f = 0; f < RW; ++f) tmp[f] = elem(b, ld, r0 + f, k, rlim, klim);
+            __builtin_memcpy(dst, tmp, LB);
           }
         }
       }
@@ -210,19 +229,20 @@ struct TileLoader {
       if constexpr (K_CONTIG) {
         const int r = item / kChunksPerRow;
         const int c = item % kChunksPerRow;
-        *reinterpret_cast<u32x4*>(dst + lds_off(r, c)) = buf[i][0];
+        u32x4 v;
+        __builtin_memcpy(&v, &buf[i][0], 16);
+        *reinterpret_cast<u32x4*>(dst + lds_off(r, c)) = v;
       } else {
-        constexpr int RB = R / CH;
+        constexpr int RB = R / RW;
         const int kb = item / RB;
         const int rb = item % RB;
-        const int r0 = rb * CH;
-        // buf[i][e] holds K-row k0+e, R-columns r0..r0+CH-1; emit R-row r0+f
-        // holding K-values k0..k0+CH-1 (chunk index kb).
-        In m[CH][CH];
+        const int r0 = rb * RW;
+        // buf[i] holds K-rows k0..k0+CH-1 of R-columns r0..r0+RW-1; emit R-row
+        // r0+f holding K-values k0..k0+CH-1 (chunk index kb).
+        In m[CH][RW];
+        __builtin_memcpy(m, &buf[i][0], CH * LB);
 #pragma unroll
-        for (int e = 0; e < CH; ++e) __builtin_memcpy(m[e], &buf[i][e], 16);
-#pragma unroll
-        for (int f = 0; f < CH; ++f) {
+        for (int f = 0; f < RW; ++f) {
           In col[CH];
 #pragma unroll
           for (int e = 0; e < CH; ++e) col[e] = m[e][f];
@@ -260,7 +280,7 @@ struct GemmArgs {
 };
 
 template <class Cfg, bool TA, bool TB, bool X3>
-__global__ __launch_bounds__(kThreads, 1) void face_gemm_kernel(GemmArgs args) {
+__global__ __launch_bounds__(64 * Cfg::WM * Cfg::WN, 1) void face_gemm_kernel(GemmArgs args) {
   using In = typename Cfg::In;
   using Out = typename Cfg::Out;
   using Acc = typename Cfg::Acc;
@@ -297,8 +317,8 @@ __global__ __launch_bounds__(kThreads, 1) void face_gemm_kernel(GemmArgs args) {
   };
 
   constexpr int NPL = USE_LO ? 2 : 1;
-  TileLoader<Cfg, BM, !TA, NPL> la;
-  TileLoader<Cfg, BN, TB, NPL> lb;
+  TileLoader<Cfg, BM, !TA, NPL, D::THREADS> la;
+  TileLoader<Cfg, BN, TB, NPL, D::THREADS> lb;
 
   const int rlim_a = args.m - m0;
   const int rlim_b = args.n - n0;
@@ -323,8 +343,8 @@ __global__ __launch_bounds__(kThreads, 1) void face_gemm_kernel(GemmArgs args) {
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int wm = (wave >> 1) * (MT * TM);  // wave origin inside the tile
-  const int wn = (wave & 1) * (NT * TM);
+  const int wm = (wave / Cfg::WN) * (MT * TM);  // wave origin inside the tile
+  const int wn = (wave % Cfg::WN) * (NT * TM);
   const int lrow = lane % TM;
   const int lgrp = lane / TM;
 
@@ -353,14 +373,9 @@ __global__ __launch_bounds__(kThreads, 1) void face_gemm_kernel(GemmArgs args) {
 #pragma unroll
     for (int kg = 0; kg < D::KG; ++kg) {
       const int c = kg * G + lgrp;
-      u32x4 fa[MT], fb[NT];
-      u32x4 fa_lo[USE_LO ? MT : 1], fb_lo[USE_LO ? NT : 1];
-#pragma unroll
-      for (int i = 0; i < MT; ++i) {
-        const int off = lds_off(wm + i * TM + lrow, c);
-        fa[i] = *reinterpret_cast<const u32x4*>(sa_hi + off);
-        if constexpr (USE_LO) fa_lo[i] = *reinterpret_cast<const u32x4*>(sa_lo + off);
-      }
+      // B fragments for the whole k-group, then one A fragment (pair) at a
+      // time, so that few fragment registers are live beside the accumulators.
+      u32x4 fb[NT], fb_lo[USE_LO ? NT : 1];
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
         const int off = lds_off(wn + j * TM + lrow, c);
@@ -368,19 +383,24 @@ __global__ __launch_bounds__(kThreads, 1) void face_gemm_kernel(GemmArgs args) {
         if constexpr (USE_LO) fb_lo[j] = *reinterpret_cast<const u32x4*>(sb_lo + off);
       }
 #pragma unroll
-      for (int i = 0; i < MT; ++i)
+      for (int i = 0; i < MT; ++i) {
+        const int off = lds_off(wm + i * TM + lrow, c);
+        const u32x4 fa = *reinterpret_cast<const u32x4*>(sa_hi + off);
+        u32x4 fa_lo;
+        if constexpr (USE_LO) fa_lo = *reinterpret_cast<const u32x4*>(sa_lo + off);
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
           if constexpr (SPLIT) {
             if constexpr (USE_LO) {
-              mma_bf16(fa_lo[i], fb[j], acc[i][j]);
-              mma_bf16(fa[i], fb_lo[j], acc[i][j]);
+              mma_bf16(fa_lo, fb[j], acc[i][j]);
+              mma_bf16(fa, fb_lo[j], acc[i][j]);
             }
-            mma_bf16(fa[i], fb[j], acc[i][j]);
+            mma_bf16(fa, fb[j], acc[i][j]);
           } else {
-            mma(Cfg{}, fa[i], fb[j], acc[i][j]);
+            mma(Cfg{}, fa, fb[j], acc[i][j]);
           }
         }
+      }
     }
 
     if (kt + 1 < nk) commit(cur ^ 1);
@@ -422,7 +442,7 @@ hipError_t launch_cfg(const GemmArgs& a0, hipStream_t s) {
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(kern, dim3(unsigned(total)), dim3(kThreads), D::LDS_BYTES, s, a);
+  hipLaunchKernelGGL(kern, dim3(unsigned(total)), dim3(D::THREADS), D::LDS_BYTES, s, a);
   return hipGetLastError();
 }
 

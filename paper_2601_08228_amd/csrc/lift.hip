@@ -113,18 +113,6 @@ __device__ __forceinline__ void store_pack(T* __restrict__ p, const Pack<T, V>& 
   }
 }
 
-// bfloat16 round-to-nearest-even of a float, as a bit pattern; NaN stays a quiet NaN.
-__device__ __forceinline__ uint16_t bf16_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x0040u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return static_cast<uint16_t>(u >> 16);
-}
-
-__device__ __forceinline__ float bf16_value(uint16_t h) {
-  return __uint_as_float(static_cast<uint32_t>(h) << 16);
-}
-
 // ---- coefficient stores ----------------------------------------------------
 template <typename T, int V>
 struct PlainStore {
@@ -141,11 +129,15 @@ struct SplitStore {
   uint16_t* __restrict__ lo;  // may be null
   int64_t P;
   __device__ __forceinline__ void put(int64_t slice, int64_t off, const Pack<float, V>& x) const {
+    // bf16 conversions round to nearest even (v_cvt_pk_bf16_f32); x - hi is
+    // exact in FP32, so lo is the correctly rounded residual.
     Pack<uint16_t, V> h, l;
 #pragma unroll
     for (int i = 0; i < V; ++i) {
-      h.v[i] = bf16_rne(x.v[i]);
-      l.v[i] = bf16_rne(x.v[i] - bf16_value(h.v[i]));
+      const __bf16 hb = static_cast<__bf16>(x.v[i]);
+      const __bf16 lb = static_cast<__bf16>(x.v[i] - static_cast<float>(hb));
+      h.v[i] = __builtin_bit_cast(uint16_t, hb);
+      l.v[i] = __builtin_bit_cast(uint16_t, lb);
     }
     store_pack<uint16_t, V>(hi + slice * P + off, h);
     if (lo != nullptr) store_pack<uint16_t, V>(lo + slice * P + off, l);

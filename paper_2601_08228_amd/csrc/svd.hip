@@ -74,6 +74,25 @@ struct SvdDims {
   int trans;  // W = slice^T (n1 < n2)
 };
 
+// FP64 reciprocal and reciprocal square root from the hardware estimates
+// (v_rcp_f64 / v_rsq_f64) refined by two Newton steps each: accurate to a few
+// units in the last place, without the scaling and fix-up sequences of the
+// correctly rounded library routines.  Arguments are finite and positive.
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double rsqrt64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+
 // Rotation that zeroes w_i.w_j, all in FP64.  With d = beta - alpha the
 // tangent t = sign(d) * 2 gamma / (|d| + sqrt(d^2 + 4 gamma^2)) is the smaller
 // root of t^2 + 2 zeta t - 1 = 0, zeta = d / (2 gamma) (Rutishauser's choice);
@@ -85,10 +104,13 @@ __device__ __forceinline__ int rotation(double al, double be, double ga, double 
   s = 0.0;
   if (!(isfinite(al) && isfinite(be) && isfinite(ga))) return 2;
   if (!(ga * ga > tol * tol * (al * be))) return 0;
+  // Here gamma != 0, so q > 0 and every argument below is positive.
   const double d = be - al;
   const double g2 = 2.0 * ga;
-  const double t = copysign(1.0, d) * g2 / (fabs(d) + sqrt(fma(d, d, g2 * g2)));
-  c = rsqrt(fma(t, t, 1.0));
+  const double q = fma(d, d, g2 * g2);
+  const double h = q * rsqrt64(q);
+  const double t = copysign(1.0, d) * g2 * rcp64(fabs(d) + h);
+  c = rsqrt64(fma(t, t, 1.0));
   s = c * t;
   return 1;
 }
@@ -388,7 +410,9 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
   const T* a = ah + int64_t(slice) * d.n1 * d.n2;
   T* W = wbuf + int64_t(slice) * nc * mr;
 
-  __shared__ T s_x[2][2][kUnits][16 * RPL];  // [round parity][top, bottom][unit][row]
+  // [round parity][top, bottom][unit][row]; 16 entries of padding per unit put
+  // the four units of a wavefront on different banks.
+  __shared__ T s_x[2][2][kUnits][16 * RPL + 16];
   __shared__ int s_rot;
   __shared__ int s_bad;
   __shared__ double s_sigma[1024];
