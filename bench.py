@@ -31,6 +31,8 @@ if ROOT not in sys.path:
 
 P, N1, N2, N3, LEV = 256, 512, 512, 512, 4
 SVD_P, SVD_N, SVD_L, SVD_K = 192, 256, 3, 20
+# Table 3 shape (Sec. IV-B): 256x192x96 hyperspectral cubes, L = 5.
+T3_N1, T3_N2, T3_P, T3_L, T3_RANKS = 256, 192, 96, 5, (2, 8, 32, 64)
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFS = 2500.0          # dense BF16 MFMA
 FP32_PEAK_TFS = 157.3
@@ -171,6 +173,33 @@ def main():
     rel_x3_fp32 = max(rel(c_x3, c32), rel(da_x3, da32), rel(db_x3, db32))
     rel_bf16_fp32 = rel(c16, c32)
 
+    # ---- w-svd vs sp-w-svd (Sec. IV-B), outside the timed steps ----------------
+    def time_call(fn, reps=3):
+        r = fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            r = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, r
+
+    x_t3 = torch.tensor(synth.hsi_like(T3_N1, T3_N2, T3_P, seed=31), dtype=torch.float32,
+                        device=dev)
+    sparse = {"table3_shape": {"n1": T3_N1, "n2": T3_N2, "p": T3_P, "L": T3_L}, "ranks": {}}
+    for rk in T3_RANKS:
+        full_ms, rf = time_call(lambda: wp.w_svd(x_t3, T3_L, rk))
+        sp_ms, rs = time_call(lambda: wp.w_svd_sparse(x_t3, T3_L, rk))
+        sparse["ranks"][str(rk)] = {
+            "w_svd_ms": round(full_ms, 4), "sp_w_svd_ms": round(sp_ms, 4),
+            "w_svd_converged": bool(rf.info.min().item() > 0),
+            "sp_w_svd_converged": bool(rs.info.min().item() > 0)}
+    sp_step_ms, rs = time_call(lambda: wp.w_svd_sparse(x_hsi, SVD_L, SVD_K, workspace=svd_ws))
+    sparse["step_tensor_sp_w_svd_ms"] = round(sp_step_ms, 4)
+    sparse["step_tensor_sp_w_svd_converged"] = bool(rs.info.min().item() > 0)
+
     if args.copy_calibration:
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -258,6 +287,7 @@ def main():
         "rel_diff_bf16_vs_fp32": rel_bf16_fp32,
         "w_svd_sweeps": [int(info.min()), int(info.max())],
         "w_svd_orth_err": [float(orth[0]), float(orth[1])],
+        "sp_w_svd": sparse,
         "roofline": roof,
         "roofline_kernels": rows,
         "cpu_baseline": cpu,

@@ -158,6 +158,23 @@ wp_status w_svd(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k,
 /* Workspace bytes for w_svd (0 on invalid arguments). */
 size_t w_svd_workspace(int64_t n1, int64_t n2, int64_t p, int L, int k, int dtype);
 
+/* ---- sp-w-svd (Sec. IV-B, computational analysis) ---------------------------
+ * Sparse variant of w_svd: only the two coarsest coefficient blocks, s_L and
+ * d_L (the leading nk = 2 p / 2^L slices of W(A)), are decomposed and
+ * truncated; the finer details d_j, j < L, are dropped, so
+ *   ak = W^{-1}(uhat_k diag(shat_k) vhat_k^T on the nk kept slices, 0 elsewhere).
+ * Arguments, signs, info and orth_err are as for w_svd, except that uhat
+ * (nk, n1, k), shat (nk, k), vhat (nk, n2, k) and info (nk) hold nk slices;
+ * ak stays (p, n1, n2).  Requires L >= 1 (WP_EINVAL otherwise).
+ */
+wp_status w_svd_sparse(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k,
+                       void* uhat, void* shat, void* vhat, void* ak, int max_sweeps,
+                       int32_t* info, double* orth_err, int dtype,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for w_svd_sparse (0 on invalid arguments). */
+size_t w_svd_sparse_workspace(int64_t n1, int64_t n2, int64_t p, int L, int k, int dtype);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,7 +38,7 @@ import numpy as np
 __all__ = [
     "check_levels", "lift_fwd", "lift_inv", "lift_fwd_adj", "lift_inv_adj",
     "face", "w_product", "w_product_vjp", "transpose", "identity", "inverse",
-    "trace", "slice_svd", "w_svd", "spatial_factors", "w_pinv", "psnr",
+    "trace", "slice_svd", "w_svd", "w_svd_sparse", "spatial_factors", "w_pinv", "psnr",
     "lsq_grad", "deblur_gd", "coefficient_weights",
 ]
 
@@ -254,6 +254,37 @@ def w_svd(a, L, k):
     vh = np.empty((p, n2, k))
     ch = np.empty((p, n1, n2))
     for c in range(p):
+        u, s, v = slice_svd(ah[c])
+        uh[c] = u[:, :k]
+        sh[c] = s[:k]
+        vh[c] = v[:, :k]
+        ch[c] = (u[:, :k] * s[:k]) @ v[:, :k].T
+    return uh, sh, vh, lift_inv(ch, L)
+
+
+def w_svd_sparse(a, L, k):
+    """Sparse w-svd, sp-w-svd (Sec. IV-B, computational analysis).
+
+    Only the coarsest coefficients carry the information kept: the s_L and
+    d_L slices (slices [0, 2m) of W(A), m = p/2^L) are decomposed and
+    truncated to rank k as in Alg. 2; the finer details d_j, j < L, are set
+    to zero before W^{-1}.  Requires L >= 1.
+
+    Returns (Uhat (2m, n1, k), shat (2m, k), Vhat (2m, n2, k), Ak (p, n1, n2)).
+    """
+    a = np.asarray(a, dtype=np.float64)
+    p, n1, n2 = a.shape
+    if L < 1:
+        raise ValueError("sp-w-svd needs L >= 1")
+    if not 1 <= k <= min(n1, n2):
+        raise ValueError("rank k out of range")
+    ah = lift_fwd(a, L)
+    kept = 2 * (p >> L)
+    uh = np.empty((kept, n1, k))
+    sh = np.empty((kept, k))
+    vh = np.empty((kept, n2, k))
+    ch = np.zeros((p, n1, n2))
+    for c in range(kept):
         u, s, v = slice_svd(ah[c])
         uh[c] = u[:, :k]
         sh[c] = s[:k]

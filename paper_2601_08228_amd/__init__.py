@@ -8,7 +8,8 @@ call and a missing build raises ImportError.
 from .wprod import (  # noqa: F401
     w_transform, w_itransform, w_transform_adj, w_itransform_adj, w_transform_split,
     w_itransform_adj_split, w_face_product, w_face_product_split, w_product,
-    w_product_workspace, w_svd, w_svd_workspace, SvdResult,
+    w_product_workspace, w_svd, w_svd_workspace, w_svd_sparse, w_svd_sparse_workspace,
+    SvdResult,
 )
 from .autograd import WProduct, w_product_ad  # noqa: F401
 from . import deblur, synth  # noqa: F401

@@ -45,6 +45,9 @@ SIGNATURES = {
     "w_svd": (_c_int, [_vp, _c_i64, _c_i64, _c_i64, _c_int, _c_int, _vp, _vp, _vp, _vp, _c_int,
                        _vp, _vp, _c_int, _vp, _sz, _vp]),
     "w_svd_workspace": (_sz, [_c_i64, _c_i64, _c_i64, _c_int, _c_int, _c_int]),
+    "w_svd_sparse": (_c_int, [_vp, _c_i64, _c_i64, _c_i64, _c_int, _c_int, _vp, _vp, _vp, _vp,
+                              _c_int, _vp, _vp, _c_int, _vp, _sz, _vp]),
+    "w_svd_sparse_workspace": (_sz, [_c_i64, _c_i64, _c_i64, _c_int, _c_int, _c_int]),
 }
 
 _lib = None

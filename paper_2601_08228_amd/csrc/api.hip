@@ -288,32 +288,38 @@ wp_status w_product(const void* a, const void* b, void* c, int64_t n1, int64_t n
   return from_hip(e);
 }
 
-size_t w_svd_workspace(int64_t n1, int64_t n2, int64_t p, int L, int k, int dtype) {
-  if (!valid_dtype(dtype)) return 0;
-  int64_t elems = 0;
-  if (check_tensor(n1, n2, p, L, &elems) != WP_OK) return 0;
-  if (k < 1 || k > n1 || k > n2 || n1 > 1024 || n2 > 1024) return 0;
-  return wp::svd_workspace_bytes(n1, n2, p, k, dtype);
+namespace {
+
+// Shared checks of w_svd and w_svd_sparse; nsl is the number of slices the
+// factors and info hold.
+wp_status check_svd(int64_t n1, int64_t n2, int64_t p, int L, int k, bool sparse, int dtype,
+                    int64_t* elems, int64_t* nsl) {
+  if (!valid_dtype(dtype)) return WP_EDTYPE;
+  const wp_status st = check_tensor(n1, n2, p, L, elems);
+  if (st != WP_OK) return st;
+  if (sparse && L < 1) return WP_EINVAL;
+  if (k < 1 || k > n1 || k > n2 || n1 > 1024 || n2 > 1024) return WP_EINVAL;
+  *nsl = sparse ? 2 * (p >> L) : p;
+  return WP_OK;
 }
 
-wp_status w_svd(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k, void* uhat,
-                void* shat, void* vhat, void* ak, int max_sweeps, int32_t* info, double* orth_err,
-                int dtype, void* ws, size_t ws_bytes, void* stream) {
-  if (!valid_dtype(dtype)) return WP_EDTYPE;
-  int64_t elems = 0;
-  wp_status st = check_tensor(n1, n2, p, L, &elems);
+wp_status run_svd_entry(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k,
+                        bool sparse, void* uhat, void* shat, void* vhat, void* ak,
+                        int max_sweeps, int32_t* info, double* orth_err, int dtype, void* ws,
+                        size_t ws_bytes, void* stream) {
+  int64_t elems = 0, nsl = 0;
+  const wp_status st = check_svd(n1, n2, p, L, k, sparse, dtype, &elems, &nsl);
   if (st != WP_OK) return st;
-  if (k < 1 || k > n1 || k > n2 || n1 > 1024 || n2 > 1024) return WP_EINVAL;
   if (a == nullptr || uhat == nullptr || shat == nullptr || vhat == nullptr || info == nullptr ||
       ws == nullptr)
     return WP_ENULL;
-  const size_t need = wp::svd_workspace_bytes(n1, n2, p, k, dtype);
+  const size_t need = wp::svd_workspace_bytes(n1, n2, p, L, k, sparse, dtype);
   if (ws_bytes < need) return WP_EWORKSPACE;
   const size_t es = dtype_size(dtype);
   const Range ra = range_of(a, elems, es);
-  const Range outs[] = {range_of(uhat, p * n1 * k, es), range_of(shat, p * k, es),
-                        range_of(vhat, p * n2 * k, es), range_of(ak, ak ? elems : 0, es),
-                        range_of(info, p, 4), range_of(orth_err, orth_err ? 2 : 0, 8),
+  const Range outs[] = {range_of(uhat, nsl * n1 * k, es), range_of(shat, nsl * k, es),
+                        range_of(vhat, nsl * n2 * k, es), range_of(ak, ak ? elems : 0, es),
+                        range_of(info, nsl, 4), range_of(orth_err, orth_err ? 2 : 0, 8),
                         Range{static_cast<const char*>(ws), static_cast<const char*>(ws) + ws_bytes}};
   constexpr int nout = sizeof(outs) / sizeof(outs[0]);
   for (int i = 0; i < nout; ++i) {
@@ -321,8 +327,37 @@ wp_status w_svd(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
     for (int j = i + 1; j < nout; ++j)
       if (overlap(outs[i], outs[j])) return WP_EALIAS;
   }
-  return from_hip(wp::launch_svd(a, n1, n2, p, L, k, uhat, shat, vhat, ak, max_sweeps, info,
-                                 orth_err, dtype, ws, static_cast<hipStream_t>(stream)));
+  return from_hip(wp::launch_svd(a, n1, n2, p, L, k, sparse, uhat, shat, vhat, ak, max_sweeps,
+                                 info, orth_err, dtype, ws, static_cast<hipStream_t>(stream)));
+}
+
+}  // namespace
+
+size_t w_svd_workspace(int64_t n1, int64_t n2, int64_t p, int L, int k, int dtype) {
+  int64_t elems = 0, nsl = 0;
+  if (check_svd(n1, n2, p, L, k, false, dtype, &elems, &nsl) != WP_OK) return 0;
+  return wp::svd_workspace_bytes(n1, n2, p, L, k, false, dtype);
+}
+
+wp_status w_svd(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k, void* uhat,
+                void* shat, void* vhat, void* ak, int max_sweeps, int32_t* info, double* orth_err,
+                int dtype, void* ws, size_t ws_bytes, void* stream) {
+  return run_svd_entry(a, n1, n2, p, L, k, false, uhat, shat, vhat, ak, max_sweeps, info,
+                       orth_err, dtype, ws, ws_bytes, stream);
+}
+
+size_t w_svd_sparse_workspace(int64_t n1, int64_t n2, int64_t p, int L, int k, int dtype) {
+  int64_t elems = 0, nsl = 0;
+  if (check_svd(n1, n2, p, L, k, true, dtype, &elems, &nsl) != WP_OK) return 0;
+  return wp::svd_workspace_bytes(n1, n2, p, L, k, true, dtype);
+}
+
+wp_status w_svd_sparse(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k,
+                       void* uhat, void* shat, void* vhat, void* ak, int max_sweeps,
+                       int32_t* info, double* orth_err, int dtype, void* ws, size_t ws_bytes,
+                       void* stream) {
+  return run_svd_entry(a, n1, n2, p, L, k, true, uhat, shat, vhat, ak, max_sweeps, info,
+                       orth_err, dtype, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

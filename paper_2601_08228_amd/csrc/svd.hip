@@ -7,29 +7,32 @@
 // n1 >= n2, its transpose otherwise); V starts as the identity.  A sweep
 // visits every column pair once, as a round-robin tournament: nc_pad - 1
 // rounds of nc_pad / 2 disjoint pairs.  For each pair, alpha = |w_i|^2,
-// beta = |w_j|^2 and gamma = w_i.w_j are formed in FP64, and when
-// |gamma| > tol * sqrt(alpha * beta) (tol = sqrt(mr) * unit roundoff of the
-// data type) the rotation angle is computed in FP64 and the rotation is
-// applied to columns i, j of W and V in the data type.  A slice has converged
-// after a sweep without rotation.
+// beta = |w_j|^2 and gamma = w_i.w_j are formed (in FP64 for FP64 data; for
+// FP32 data in FP32 by the register-resident kernel and in FP64 by the
+// general one), and when |gamma| > tol * sqrt(alpha * beta) (tol = sqrt(mr) *
+// unit roundoff of the data type) the rotation angle is computed in FP64 and
+// the rotation is applied to columns i, j of W (and V) in the data type.  A
+// slice has converged after a sweep without rotation.
 //
-// Register-resident kernel (mr <= 256, nc <= 256): every wavefront keeps S
-// column pairs of W in registers, one pair slot per tournament pair.  Slot q
-// holds tournament positions q (top) and NP-1-q (bottom); between rounds the
-// columns advance one step around the circle of positions 1..NP-1 (position 0
-// is fixed), which is a register shift inside a wavefront plus one column in
-// each direction through LDS between neighbouring wavefronts.  The FP64 dot
-// products of a batch of pairs are reduced with one reduce-scatter butterfly,
-// the angles of the batch are computed side by side in one lane per pair and
-// broadcast with readlane.  V lives in the workspace (L2-resident) and is
-// updated one round behind, so its loads overlap the next batch's work.
-// A general kernel keeps W in the workspace as well and covers the larger
-// shapes.
+// Register-resident kernel (the columns of a slice fit the registers of one
+// workgroup): 32 units of 16 lanes each hold J tournament slots (a top and a
+// bottom column per slot), rows spread over the unit's lanes.  alpha, beta,
+// gamma are row sums inside a unit (DPP), the J angles of a unit are
+// evaluated side by side in FP64 and broadcast, and the circle advance of
+// the round-robin tournament is a renaming of register slots plus two
+// columns per unit through LDS.  Only W is kept; the second factor is
+// recovered from A V = U Sigma afterwards and orthonormalised.  A general
+// kernel keeps W and V in the workspace and covers the larger shapes.
+//
+// sp-w-svd (Sec. IV-B) runs the same kernels on the s_L and d_L slices only
+// and leaves the finer details zero in the rebuild.
 //
 // Afterwards sigma_i = |w_i| (FP64), the columns are ranked by decreasing
 // sigma (ties by index), the k leading ones are normalised into U, signs are
 // fixed so that each U column's largest-magnitude entry is positive, and
 // U * sigma is written for the rebuild.
+
+#include <type_traits>
 
 #include "wp_internal.h"
 
@@ -336,53 +339,51 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_global_kernel(
   if (threadIdx.x == 0) info[slice] = (converged && s_bad == 0) ? sweeps : -sweeps;
 }
 
-// DPP move of a 64-bit value within rows of 16 lanes (CTRL: DPP control word).
+// Cross-lane moves inside rows of 16 lanes.  CTRL is a DPP control word; all
+// controls used here read a valid lane, so the moves need no old value.
 template <int CTRL>
-__device__ __forceinline__ double dpp64(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+__device__ __forceinline__ float dpp_f32(float x) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, true);
   return __hiloint2double(hi, lo);
 }
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_move(T x) {
+  if constexpr (sizeof(T) == 8)
+    return dpp_f64<CTRL>(x);
+  else
+    return dpp_f32<CTRL>(x);
+}
 
-// Sum over the 16 lanes of a DPP row.  Every step adds a value and its partner
-// (rotate by 8 and by 4 within the row, then swap pairs of 2 and of 1 within
-// quads), and each partial is formed as a + b in one lane and b + a in the
-// other, so all 16 lanes end with the same bits.
-__device__ __forceinline__ double row_sum16(double x) {
-  x += dpp64<0x128>(x);  // row_ror:8
-  x += dpp64<0x124>(x);  // row_ror:4
-  x += dpp64<0x4e>(x);   // quad_perm [2,3,0,1]
-  x += dpp64<0xb1>(x);   // quad_perm [1,0,3,2]
+// Sum over the 16 lanes of a row: rotate by 8 and by 4 inside the row, then
+// swap pairs of 2 and of 1 inside quads.  Each step adds two values in both
+// partner lanes (a + b and b + a), so all 16 lanes end with the same bits.
+// In FP32 the move is fused into the add (v_add_f32 with DPP).
+template <typename T>
+__device__ __forceinline__ T row_sum16(T x) {
+  x += dpp_move<0x128>(x);  // row_ror:8
+  x += dpp_move<0x124>(x);  // row_ror:4
+  x += dpp_move<0x4e>(x);   // quad_perm [2,3,0,1]
+  x += dpp_move<0xb1>(x);   // quad_perm [1,0,3,2]
   return x;
 }
 
-// Per-lane partial of the three dot products over the RPL rows a lane holds.
-// FP64 data accumulates in FP64.  FP32 data accumulates its (at most 16)
-// terms in FP32 and the partials are summed across the row in FP64, so the
-// error of gamma relative to |w_i||w_j| stays near 2^-24, below the rotation
-// threshold sqrt(mr) 2^-24.
-template <typename T, int RPL>
-__device__ __forceinline__ void lane_dots(const T (&x)[RPL], const T (&y)[RPL], double& al,
-                                          double& be, double& ga) {
-  if constexpr (sizeof(T) == 8) {
-    al = be = ga = 0;
-#pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-      al = fma(x[t], x[t], al);
-      be = fma(y[t], y[t], be);
-      ga = fma(x[t], y[t], ga);
-    }
-  } else {
-    float a = 0.f, b = 0.f, g = 0.f;
-#pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-      a = fmaf(x[t], x[t], a);
-      b = fmaf(y[t], y[t], b);
-      g = fmaf(x[t], y[t], g);
-    }
-    al = a;
-    be = b;
-    ga = g;
+// Value of lane L of the row, in every lane of the row (row_newbcast).
+template <int L, typename T>
+__device__ __forceinline__ T row_bcast(T x) {
+  return dpp_move<0x150 + L>(x);
+}
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
   }
 }
 
@@ -390,37 +391,58 @@ constexpr int kUnits = 4 * kJacobiWaves;  // 16-lane rows per workgroup
 
 // Register-resident Jacobi on W only.  A unit is one 16-lane DPP row; column
 // entries are spread over its lanes, RPL rows per lane (row = lane16 + 16 t,
-// mr <= 16 * RPL).  Each unit owns J consecutive tournament slots and works on
-// one of its pairs at a time, so a wavefront rotates four pairs at once.
-// nunits * J slots in total, NP = 2 * nunits * J positions (positions beyond
-// nc hold zero columns, which never rotate).
+// mr <= 16 * RPL).  Unit u owns the J consecutive tournament slots uJ..uJ+J-1
+// (a top and a bottom column each), so a wavefront works on 4 J pairs per
+// round.  nunits * J slots in total; positions beyond nc hold zero columns,
+// which never rotate.
+//
+// Per round and pair: alpha, beta and gamma as 16-lane row sums (FP32 data:
+// FP32 lane partials and FP32 row sums, at most RPL + 4 rounding steps, well
+// under the threshold sqrt(mr) * 2^-24 in the typical case; FP64 data: FP64
+// throughout).  The J angles of a unit are then evaluated together in FP64,
+// pair j in lane j, and broadcast to the row.
+//
+// Circle method: position 0 (unit 0, top slot 0) is fixed and the other
+// positions advance one step per round (top q -> top q+1, top H-1 -> bottom
+// H-1, bottom q -> bottom q-1, bottom 0 -> top 1).  Inside a unit this is a
+// renaming of the J register slots, so the round loop is unrolled J times and
+// at unrolled step rr logical top j lives in register slot (j - rr) mod J and
+// logical bottom j in slot (j + rr) mod J.  Only the unit's last top and
+// first bottom column leave it, through LDS, into the slots that they vacate.
+// Unit 0 also passes its fixed column through LDS and takes its own first
+// bottom column into top slot 1.
 template <typename T, int J, int RPL>
 __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
     const T* __restrict__ ah, T* __restrict__ wbuf, SvdDims d, int nunits, int max_sweeps,
     T* __restrict__ uhat, T* __restrict__ shat, T* __restrict__ vhat, T* __restrict__ us,
     int32_t* __restrict__ info) {
+  static_assert(J == 1 || J == 2 || J == 4, "J is 1, 2 or 4");
+  constexpr int M = J - 1;
+  constexpr int SLOT = 16 * RPL + 16;  // padding puts the 4 units of a wave on other banks
+  constexpr int PAR = 2 * kUnits * SLOT;
   const int slice = blockIdx.x;
   const int lane16 = threadIdx.x & 15;
   const int unit = threadIdx.x >> 4;
   const int mr = d.mr, nc = d.nc;
   const int H = nunits * J;
-  const int CIRC = 2 * H - 1;            // positions 1..NP-1 form the circle
+  const int CIRC = 2 * H - 1;
   const bool active = unit < nunits;
-  const int q0 = unit * J;               // first slot of this unit
+  const int last = nunits - 1;
+  const int q0 = unit * J;
   const T* a = ah + int64_t(slice) * d.n1 * d.n2;
   T* W = wbuf + int64_t(slice) * nc * mr;
 
-  // [round parity][top, bottom][unit][row]; 16 entries of padding per unit put
-  // the four units of a wavefront on different banks.
-  __shared__ T s_x[2][2][kUnits][16 * RPL + 16];
-  __shared__ int s_rot;
+  // [round parity][outgoing top, outgoing bottom][unit][row]
+  __shared__ T s_x[2][2][kUnits][SLOT];
+  __shared__ T s_fx[2][SLOT];  // unit 0's fixed column
+  __shared__ int s_rot[2];
   __shared__ int s_bad;
   __shared__ double s_sigma[1024];
   __shared__ int s_order[1024];
 
-  // Column held by slot q in round r (0 <= r < CIRC): the circle advances one
-  // position per round and position p initially holds column p.
-  // (0 <= q-1, 2H-2-q < CIRC and 0 <= r < CIRC, so one conditional wrap suffices.)
+  // Column held by slot q after r rounds (0 <= r < CIRC): position p starts
+  // with column p and the circle advances one position per round.
+  // (0 <= q-1, 2H-2-q < CIRC, so one conditional wrap suffices.)
   auto wrap = [&](int x) { return (x < 0 ? x + CIRC : x) + 1; };
   auto top_id = [&](int q, int r) { return q == 0 ? 0 : wrap(q - 1 - r); };
   auto bot_id = [&](int q, int r) { return wrap(2 * H - 2 - q - r); };
@@ -428,7 +450,35 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
     return d.trans ? a[c * d.n2 + row] : a[row * d.n2 + c];
   };
 
-  T top[J][RPL], bot[J][RPL];
+  // Where the columns entering this unit come from (parity 0 addresses).
+  // New top 0: unit 0 keeps its fixed column; with J == 1 unit 1 takes unit
+  // 0's first bottom; otherwise the left neighbour's last top.  New bottom
+  // J-1: the right neighbour's first bottom; the last unit takes its own
+  // last top (its own first bottom when H == 1, where nothing moves).
+  // Units past the last one hold zero columns and read back their own
+  // outgoing (zero) columns, so they never rotate.
+  const T* in_top;
+  int in_top_par = PAR;
+  const T* in_bot;
+  if (!active) {
+    in_top = &s_x[0][0][unit][0];
+    in_bot = &s_x[0][1][unit][0];
+  } else {
+    if (unit == 0) {
+      in_top = &s_fx[0][0];
+      in_top_par = SLOT;
+    } else {
+      in_top = (J == 1 && unit == 1) ? &s_x[0][1][0][0] : &s_x[0][0][unit - 1][0];
+    }
+    in_bot = unit < last ? &s_x[0][1][unit + 1][0]
+                         : (H == 1 ? &s_x[0][1][unit][0] : &s_x[0][0][unit][0]);
+  }
+  // Every unit runs the same instructions (no branch around the round body,
+  // which keeps the renamed register slots in place); a wavefront without an
+  // active unit works on zero columns.
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+
+  T tc[J][RPL], bc[J][RPL];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int it = top_id(q0 + j, 0), ib = bot_id(q0 + j, 0);
@@ -436,107 +486,142 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
     for (int t = 0; t < RPL; ++t) {
       const int row = lane16 + 16 * t;
       const bool ok = active && row < mr;
-      top[j][t] = (ok && it < nc) ? w_src(row, it) : T(0);
-      bot[j][t] = (ok && ib < nc) ? w_src(row, ib) : T(0);
+      tc[j][t] = (ok && it < nc) ? w_src(row, it) : T(0);
+      bc[j][t] = (ok && ib < nc) ? w_src(row, ib) : T(0);
     }
   }
-  if (threadIdx.x == 0) s_bad = 0;
+  if (threadIdx.x == 0) {
+    s_bad = 0;
+    s_rot[0] = 0;
+    s_rot[1] = 0;
+  }
   __syncthreads();
 
   const double tol = sqrt(double(mr)) * Unit<T>::value;
-  int sweeps = 0;
-  bool converged = false;
-  for (int sw = 0; sw < max_sweeps; ++sw) {
-    if (threadIdx.x == 0) s_rot = 0;
-    __syncthreads();
-    int my_rot = 0;
-    bool my_bad = false;
-    for (int r = 0; r < CIRC; ++r) {
-      if (active) {
+  int sw = 0, par = 0, my_rot = 0;
+  bool my_bad = false, converged = false;
+
+  // A sweep runs 2H = CIRC + 1 rounds, a whole number of J-round blocks, so
+  // the register renaming is the identity at every sweep end (the extra
+  // round repeats the pairs of the sweep's first round).
+  for (;;) {
+    for (int blk = 0; blk < 2 * nunits; ++blk) {
+      static_for<0, J>([&](auto RR) {
+        constexpr int rr = decltype(RR)::value;
+        {
+          T al[J], be[J], ga[J];
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-          double al, be, ga;
-          lane_dots<T, RPL>(top[j], bot[j], al, be, ga);
-          al = row_sum16(al);
-          be = row_sum16(be);
-          ga = row_sum16(ga);
-          double cd, sd;
-          const int flag = rotation(al, be, ga, tol, cd, sd);
-          my_bad |= flag == 2;
-          if (flag == 1) {
-            const T c = T(cd), sn = T(sd);
-            ++my_rot;
+          for (int j = 0; j < J; ++j) {
+            const T* x = tc[(j - rr) & M];
+            const T* y = bc[(j + rr) & M];
+            T pa = 0, pb = 0, pg = 0;
 #pragma unroll
             for (int t = 0; t < RPL; ++t) {
-              const T x = top[j][t], y = bot[j][t];
-              top[j][t] = c * x - sn * y;
-              bot[j][t] = sn * x + c * y;
+              pa = fma(x[t], x[t], pa);
+              pb = fma(y[t], y[t], pb);
+              pg = fma(x[t], y[t], pg);
+            }
+            al[j] = row_sum16(pa);
+            be[j] = row_sum16(pb);
+            ga[j] = row_sum16(pg);
+          }
+          // Pair j's angle in lane j.
+          T sa = al[0], sb = be[0], sg = ga[0];
+#pragma unroll
+          for (int j = 1; j < J; ++j) {
+            if (lane16 == j) {
+              sa = al[j];
+              sb = be[j];
+              sg = ga[j];
+            }
+          }
+          double cd, sd;
+          const int flag = rotation(double(sa), double(sb), double(sg), tol, cd, sd);
+          if (lane16 < J) {
+            my_rot += flag == 1;
+            my_bad |= flag == 2;
+          }
+          const T cl = T(cd), sl = T(sd);
+          static_for<0, J>([&](auto JJ) {
+            constexpr int j = decltype(JJ)::value;
+            const T c = row_bcast<j>(cl), s = row_bcast<j>(sl);
+            T* x = tc[(j - rr) & M];
+            T* y = bc[(j + rr) & M];
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+              const T cu = c * x[t], su = s * x[t];
+              x[t] = fma(-s, y[t], cu);
+              y[t] = fma(c, y[t], su);
+            }
+          });
+          // Outgoing columns: logical top J-1 and bottom 0 (and unit 0's fixed top 0).
+          T* ot = &s_x[0][0][unit][0] + par * PAR;
+          T* ob = &s_x[0][1][unit][0] + par * PAR;
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) {
+            ot[lane16 + 16 * t] = tc[(M - rr) & M][t];
+            ob[lane16 + 16 * t] = bc[rr & M][t];
+          }
+          if (wave == 0) {
+            T* fx = &s_fx[0][0] + par * SLOT;
+            if (unit == 0) {
+#pragma unroll
+              for (int t = 0; t < RPL; ++t) fx[lane16 + 16 * t] = tc[(J - rr) & M][t];
             }
           }
         }
-        // Boundary columns for the neighbouring units.
+        __syncthreads();
+        {
+          // Incoming columns land in the register slots the outgoing ones left.
+          const T* it = in_top + par * in_top_par;
+          const T* ib = in_bot + par * PAR;
 #pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          s_x[r & 1][0][unit][lane16 + 16 * t] = top[J - 1][t];
-          s_x[r & 1][1][unit][lane16 + 16 * t] = bot[0][t];
+          for (int t = 0; t < RPL; ++t) {
+            tc[(M - rr) & M][t] = it[lane16 + 16 * t];
+            bc[rr & M][t] = ib[lane16 + 16 * t];
+          }
+          if (J > 1 && wave == 0) {
+            // Unit 0's top 1 takes its own former bottom 0.
+            const T* b0 = &s_x[0][1][0][0] + par * PAR;
+            const bool u0 = unit == 0;
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+              const T v = b0[lane16 + 16 * t];
+              tc[(J - rr) & M][t] = u0 ? v : tc[(J - rr) & M][t];
+            }
+          }
         }
-      }
-      __syncthreads();
-      if (active) {
-        // Advance the circle by one position: top[q] -> top[q+1], top[H-1] ->
-        // bottom[H-1], bottom[q] -> bottom[q-1], bottom[0] -> top[1]; top[0] stays.
-        const int q1 = q0 + J - 1;
-        T first[RPL], last[RPL];
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const int row = lane16 + 16 * t;
-          first[t] = q0 == 0 ? top[0][t]
-                             : (q0 == 1 ? s_x[r & 1][1][0][row] : s_x[r & 1][0][unit - 1][row]);
-          // (with a single slot, top[0] is the fixed position and nothing moves)
-          last[t] = q1 == H - 1 ? (H == 1 ? bot[J - 1][t] : top[J - 1][t])
-                                : s_x[r & 1][1][unit + 1][row];
-        }
-#pragma unroll
-        for (int j = J - 1; j >= 1; --j)
-#pragma unroll
-          for (int t = 0; t < RPL; ++t) top[j][t] = (q0 + j == 1) ? bot[0][t] : top[j - 1][t];
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) top[0][t] = first[t];
-#pragma unroll
-        for (int j = 0; j < J - 1; ++j)
-#pragma unroll
-          for (int t = 0; t < RPL; ++t) bot[j][t] = bot[j + 1][t];
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) bot[J - 1][t] = last[t];
-      }
+        par ^= 1;
+      });
     }
-    // One count per unit (all 16 lanes of a unit took the same decisions).
-    if (active && lane16 == 0 && my_rot) atomicAdd(&s_rot, my_rot);
-    if (active && lane16 == 0 && my_bad) s_bad = 1;
+    // End of a sweep: converged if no pair rotated.
+    const int sp = sw & 1;
+    if (my_rot) atomicAdd(&s_rot[sp], my_rot);
+    if (my_bad) s_bad = 1;
+    my_rot = 0;
     __syncthreads();
-    sweeps = sw + 1;
-    const bool done = (s_rot == 0);
-    const bool bad = (s_bad != 0);
-    __syncthreads();
-    if (bad) break;
-    if (done) {
-      converged = true;
+    const bool done = s_rot[sp] == 0;
+    const bool bad = s_bad != 0;
+    if (threadIdx.x == 0) s_rot[sp ^ 1] = 0;
+    ++sw;
+    if (bad || done || sw >= max_sweeps) {
+      converged = done && !bad;
       break;
     }
   }
 
   if (active) {
-    // W back to the workspace (after whole sweeps every slot holds its initial
-    // columns again).
+    // After sw sweeps the circle has advanced sw * 2H = sw (mod CIRC) positions.
+    const int r = sw % CIRC;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      const int it = top_id(q0 + j, 0), ib = bot_id(q0 + j, 0);
+      const int cti = top_id(q0 + j, r), cbi = bot_id(q0 + j, r);
 #pragma unroll
       for (int t = 0; t < RPL; ++t) {
         const int row = lane16 + 16 * t;
         if (row < mr) {
-          if (it < nc) W[it * mr + row] = top[j][t];
-          if (ib < nc) W[ib * mr + row] = bot[j][t];
+          if (cti < nc) W[cti * mr + row] = tc[j][t];
+          if (cbi < nc) W[cbi * mr + row] = bc[j][t];
         }
       }
     }
@@ -544,7 +629,7 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
   __syncthreads();
   emit_factors<T>(W, static_cast<const T*>(nullptr), d, slice, uhat, shat, vhat, us, s_sigma,
                   s_order);
-  if (threadIdx.x == 0) info[slice] = (converged && s_bad == 0) ? sweeps : -sweeps;
+  if (threadIdx.x == 0) info[slice] = converged ? sw : -sw;
 }
 
 // The factor the register-resident kernel did not form, from A V = U Sigma:
@@ -710,7 +795,9 @@ struct SvdPlan {
   size_t ah, w, v, us, part, total;
 };
 
-inline SvdPlan plan_svd(int64_t n1, int64_t n2, int64_t p, int k, size_t es) {
+// p coefficient slices are lifted; the first nsl of them are decomposed
+// (nsl = p for w-svd, 2 p / 2^L for sp-w-svd).
+inline SvdPlan plan_svd(int64_t n1, int64_t n2, int64_t p, int64_t nsl, int k, size_t es) {
   const int64_t mr = n1 > n2 ? n1 : n2;
   const int64_t nc = n1 > n2 ? n2 : n1;
   SvdPlan pl{};
@@ -721,19 +808,30 @@ inline SvdPlan plan_svd(int64_t n1, int64_t n2, int64_t p, int k, size_t es) {
     return at;
   };
   pl.ah = take(size_t(p * n1 * n2) * es);  // coefficients, later the rebuilt ones
-  pl.w = take(size_t(p * nc * mr) * es);
-  pl.v = take(size_t(p * nc * nc) * es);
-  pl.us = take(size_t(p * n1 * k) * es);
-  pl.part = take(size_t(p) * 2 * sizeof(double));
+  pl.w = take(size_t(nsl * nc * mr) * es);
+  pl.v = take(size_t(nsl * nc * nc) * es);
+  pl.us = take(size_t(nsl * n1 * k) * es);
+  pl.part = take(size_t(nsl) * 2 * sizeof(double));
   pl.total = off + 256;
   return pl;
 }
 
+// Zeroes x[0, n) with plain vector stores (no memset node, so the call
+// sequence stays capturable).
 template <typename T>
-hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, T* uhat, T* shat,
-                   T* vhat, T* ak, int max_sweeps, int32_t* info, double* orth_err, void* ws,
-                   hipStream_t s) {
-  const SvdPlan pl = plan_svd(n1, n2, p, k, sizeof(T));
+__global__ __launch_bounds__(256) void zero_kernel(T* __restrict__ x, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    x[i] = T(0);
+}
+
+template <typename T>
+hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, bool sparse,
+                   T* uhat, T* shat, T* vhat, T* ak, int max_sweeps, int32_t* info,
+                   double* orth_err, void* ws, hipStream_t s) {
+  // sp-w-svd decomposes only s_L and d_L, the leading 2 p / 2^L coefficient
+  // slices; the finer details are dropped (zero) in the rebuild.
+  const int64_t nsl = sparse ? 2 * (p >> L) : p;
+  const SvdPlan pl = plan_svd(n1, n2, p, nsl, k, sizeof(T));
   char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
   T* ah = reinterpret_cast<T*>(base + pl.ah);
   T* w = reinterpret_cast<T*>(base + pl.w);
@@ -761,7 +859,7 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
   d.trans = n1 < n2 ? 1 : 0;
   if (max_sweeps <= 0) max_sweeps = sizeof(T) == 8 ? 30 : 20;
 
-  const dim3 grid{unsigned(p)};
+  const dim3 grid{unsigned(nsl)};
   const dim3 block{unsigned(kJacobiThreads)};
   // Register-resident kernel when the columns fit: each of up to 32 units
   // (16-lane rows) owns J slots, J the smallest power of two with
@@ -787,7 +885,7 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
 #undef WP_JREG
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((recover_kernel<T>), dim3(unsigned(p * k)), dim3(256), 0, s, ah, d, uhat,
+    hipLaunchKernelGGL((recover_kernel<T>), dim3(unsigned(nsl * k)), dim3(256), 0, s, ah, d, uhat,
                        shat, vhat, us);
   } else if (d.mr <= 64) {
     hipLaunchKernelGGL((jacobi_global_kernel<T, 1>), grid, block, 0, s, ah, w, v, d, max_sweeps, uhat, shat, vhat, us, info);
@@ -806,15 +904,24 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
   if (ak != nullptr) {
     // Rebuild Chat = (U sigma) V^T per slice (a face-product with inner size k),
     // reusing the coefficient region, then W^{-1}.
+    if (nsl < p) {
+      const int64_t tail = (p - nsl) * n1 * n2;
+      const int64_t want = (tail + 255) / 256;
+      const int64_t blocks = want < 8192 ? want : 8192;
+      hipLaunchKernelGGL((zero_kernel<T>), dim3(unsigned(blocks)), dim3(256), 0, s,
+                         ah + nsl * n1 * n2, tail);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     if constexpr (sizeof(T) == 8) {
       e = launch_face_f64(reinterpret_cast<const double*>(us), reinterpret_cast<const double*>(vhat),
-                          reinterpret_cast<double*>(ah), n1, k, n2, p, false, true, s);
+                          reinterpret_cast<double*>(ah), n1, k, n2, nsl, false, true, s);
       if (e == hipSuccess)
         e = launch_lift_f64(LiftKind::kInverse, reinterpret_cast<const double*>(ah),
                             reinterpret_cast<double*>(ak), n1 * n2, p, L, s);
     } else {
       e = launch_face_f32(reinterpret_cast<const float*>(us), reinterpret_cast<const float*>(vhat),
-                          reinterpret_cast<float*>(ah), n1, k, n2, p, false, true, s);
+                          reinterpret_cast<float*>(ah), n1, k, n2, nsl, false, true, s);
       if (e == hipSuccess)
         e = launch_lift_f32(LiftKind::kInverse, reinterpret_cast<const float*>(ah),
                             reinterpret_cast<float*>(ak), n1 * n2, p, L, s);
@@ -827,18 +934,18 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
     // recovered columns as they are: their product with U is the exact rank-k
     // projection U U^T A).
     if (d.trans)
-      hipLaunchKernelGGL((polish_kernel<T>), dim3(unsigned(p)), dim3(256), 0, s, uhat, int(n1), k);
+      hipLaunchKernelGGL((polish_kernel<T>), dim3(unsigned(nsl)), dim3(256), 0, s, uhat, int(n1), k);
     else
-      hipLaunchKernelGGL((polish_kernel<T>), dim3(unsigned(p)), dim3(256), 0, s, vhat, int(n2), k);
+      hipLaunchKernelGGL((polish_kernel<T>), dim3(unsigned(nsl)), dim3(256), 0, s, vhat, int(n2), k);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
 
   if (orth_err != nullptr) {
-    hipLaunchKernelGGL((orth_kernel<T>), dim3(unsigned(p)), dim3(256), 0, s, uhat, int(n1), k, part);
-    hipLaunchKernelGGL((orth_kernel<T>), dim3(unsigned(p)), dim3(256), 0, s, vhat, int(n2), k, part + p);
-    hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, s, part, p, orth_err);
-    hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, s, part + p, p, orth_err + 1);
+    hipLaunchKernelGGL((orth_kernel<T>), dim3(unsigned(nsl)), dim3(256), 0, s, uhat, int(n1), k, part);
+    hipLaunchKernelGGL((orth_kernel<T>), dim3(unsigned(nsl)), dim3(256), 0, s, vhat, int(n2), k, part + nsl);
+    hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, s, part, nsl, orth_err);
+    hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, s, part + nsl, nsl, orth_err + 1);
     e = hipGetLastError();
   }
   return e;
@@ -846,18 +953,21 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
 
 }  // namespace
 
-size_t svd_workspace_bytes(int64_t n1, int64_t n2, int64_t p, int k, int dtype) {
-  return plan_svd(n1, n2, p, k, dtype == 0 ? 8 : 4).total;
+size_t svd_workspace_bytes(int64_t n1, int64_t n2, int64_t p, int L, int k, bool sparse,
+                           int dtype) {
+  return plan_svd(n1, n2, p, sparse ? 2 * (p >> L) : p, k, dtype == 0 ? 8 : 4).total;
 }
 
-hipError_t launch_svd(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k, void* uhat,
-                      void* shat, void* vhat, void* ak, int max_sweeps, int32_t* info,
+hipError_t launch_svd(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k, bool sparse,
+                      void* uhat, void* shat, void* vhat, void* ak, int max_sweeps, int32_t* info,
                       double* orth_err, int dtype, void* ws, hipStream_t s) {
   if (dtype == 0)
-    return run_svd<double>(static_cast<const double*>(a), n1, n2, p, L, k, static_cast<double*>(uhat),
+    return run_svd<double>(static_cast<const double*>(a), n1, n2, p, L, k, sparse,
+                           static_cast<double*>(uhat),
                            static_cast<double*>(shat), static_cast<double*>(vhat),
                            static_cast<double*>(ak), max_sweeps, info, orth_err, ws, s);
-  return run_svd<float>(static_cast<const float*>(a), n1, n2, p, L, k, static_cast<float*>(uhat),
+  return run_svd<float>(static_cast<const float*>(a), n1, n2, p, L, k, sparse,
+                        static_cast<float*>(uhat),
                         static_cast<float*>(shat), static_cast<float*>(vhat), static_cast<float*>(ak),
                         max_sweeps, info, orth_err, ws, s);
 }

@@ -42,9 +42,12 @@ hipError_t launch_face_bf16(const uint16_t* ahi, const uint16_t* alo, const uint
                             int64_t batch, bool ta, bool tb, bool x3, hipStream_t s);
 
 // w-svd pieces (see svd.hip).
-size_t svd_workspace_bytes(int64_t n1, int64_t n2, int64_t p, int k, int dtype);
+// sparse = true decomposes only s_L and d_L (sp-w-svd); outputs then hold
+// 2 p / 2^L slices.
+size_t svd_workspace_bytes(int64_t n1, int64_t n2, int64_t p, int L, int k, bool sparse,
+                           int dtype);
 hipError_t launch_svd(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k,
-                      void* uhat, void* shat, void* vhat, void* ak, int max_sweeps,
+                      bool sparse, void* uhat, void* shat, void* vhat, void* ak, int max_sweeps,
                       int32_t* info, double* orth_err, int dtype, void* ws, hipStream_t s);
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }

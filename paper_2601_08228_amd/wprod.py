@@ -19,7 +19,7 @@ __all__ = [
     "w_transform", "w_itransform", "w_transform_adj", "w_itransform_adj",
     "w_transform_split", "w_itransform_adj_split", "w_face_product",
     "w_face_product_split", "w_product", "w_product_workspace", "w_svd",
-    "w_svd_workspace", "SvdResult",
+    "w_svd_workspace", "w_svd_sparse", "w_svd_sparse_workspace", "SvdResult",
 ]
 
 _DT = {torch.float64: _lib.WP_F64, torch.float32: _lib.WP_F32}
@@ -192,6 +192,35 @@ def w_svd_workspace(n1, n2, p, L, k, dtype=torch.float32):
     return int(_lib.load().w_svd_workspace(n1, n2, p, int(L), int(k), _DT[dtype]))
 
 
+def w_svd_sparse_workspace(n1, n2, p, L, k, dtype=torch.float32):
+    return int(_lib.load().w_svd_sparse_workspace(n1, n2, p, int(L), int(k), _DT[dtype]))
+
+
+def _svd_call(name, a, L, k, nsl, max_sweeps, want_ak, want_orth, workspace):
+    _dev_tensor(a, "a", tuple(_DT))
+    p, n1, n2 = a.shape
+    k = int(k)
+    dev = a.device
+    nsl = max(int(nsl), 0)
+    uhat = torch.empty((nsl, n1, k), dtype=a.dtype, device=dev)
+    shat = torch.empty((nsl, k), dtype=a.dtype, device=dev)
+    vhat = torch.empty((nsl, n2, k), dtype=a.dtype, device=dev)
+    ak = torch.empty_like(a) if want_ak else None
+    info = torch.empty((nsl,), dtype=torch.int32, device=dev)
+    orth = torch.empty((2,), dtype=torch.float64, device=dev) if want_orth else None
+    lib = _lib.load()
+    need = getattr(lib, name + "_workspace")(n1, n2, p, int(L), k, _DT[a.dtype])
+    if workspace is None:
+        workspace = torch.empty(max(int(need), 1), dtype=torch.uint8, device=dev)
+    with torch.cuda.device(dev):
+        st = getattr(lib, name)(_ptr(a), n1, n2, p, int(L), k, _ptr(uhat), _ptr(shat), _ptr(vhat),
+                                _ptr(ak), int(max_sweeps), _ptr(info), _ptr(orth), _DT[a.dtype],
+                                _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                _stream(a))
+    _lib.check(name, st)
+    return SvdResult(uhat, shat, vhat, ak, info, orth)
+
+
 def w_svd(a, L, k, max_sweeps=0, want_ak=True, want_orth=True, workspace=None):
     """Truncated w-svd (Alg. 2): wavelet-domain factors, rank-k approximation, Jacobi info.
 
@@ -199,23 +228,16 @@ def w_svd(a, L, k, max_sweeps=0, want_ak=True, want_orth=True, workspace=None):
     info (p,) int32 device tensor, orth_err (2,) float64 device tensor or None).
     Nothing is synchronised; info[k] < 0 marks a slice that did not converge.
     """
-    _dev_tensor(a, "a", tuple(_DT))
-    p, n1, n2 = a.shape
-    k = int(k)
-    dev = a.device
-    uhat = torch.empty((p, n1, k), dtype=a.dtype, device=dev)
-    shat = torch.empty((p, k), dtype=a.dtype, device=dev)
-    vhat = torch.empty((p, n2, k), dtype=a.dtype, device=dev)
-    ak = torch.empty_like(a) if want_ak else None
-    info = torch.empty((p,), dtype=torch.int32, device=dev)
-    orth = torch.empty((2,), dtype=torch.float64, device=dev) if want_orth else None
-    need = w_svd_workspace(n1, n2, p, L, k, a.dtype)
-    if workspace is None:
-        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
-    with torch.cuda.device(dev):
-        st = _lib.load().w_svd(_ptr(a), n1, n2, p, int(L), k, _ptr(uhat), _ptr(shat), _ptr(vhat),
-                               _ptr(ak), int(max_sweeps), _ptr(info), _ptr(orth), _DT[a.dtype],
-                               _ptr(workspace), workspace.numel() * workspace.element_size(),
-                               _stream(a))
-    _lib.check("w_svd", st)
-    return SvdResult(uhat, shat, vhat, ak, info, orth)
+    p = a.shape[0] if a.dim() == 3 else 0
+    return _svd_call("w_svd", a, L, k, p, max_sweeps, want_ak, want_orth, workspace)
+
+
+def w_svd_sparse(a, L, k, max_sweeps=0, want_ak=True, want_orth=True, workspace=None):
+    """sp-w-svd (Sec. IV-B): w-svd of the s_L and d_L slices only, finer details dropped.
+
+    Same results as w_svd, but the factors and info hold nk = 2 p / 2^L slices
+    (s_L then d_L); ak is (p, n1, n2).  Needs L >= 1.
+    """
+    p = a.shape[0] if a.dim() == 3 else 0
+    nsl = 2 * (p >> int(L)) if int(L) >= 1 else 0
+    return _svd_call("w_svd_sparse", a, L, k, nsl, max_sweeps, want_ak, want_orth, workspace)

@@ -31,7 +31,8 @@ def test_header_declares_expected_entry_points():
     for must in ["w_transform", "w_itransform", "w_transform_adj", "w_itransform_adj",
                  "w_transform_split", "w_itransform_adj_split", "w_face_product",
                  "w_face_product_split", "w_product", "w_product_workspace", "w_svd",
-                 "w_svd_workspace", "w_status_string", "w_version"]:
+                 "w_svd_workspace", "w_svd_sparse", "w_svd_sparse_workspace",
+                 "w_status_string", "w_version"]:
         assert must in names, must
 
 
@@ -137,6 +138,26 @@ def test_svd_validation(lib):
     assert f(A, 8, 6, 16, 2, 3, U, S, V, AK, 0, INFO, ORTH, 1, W, need - 1, NULL) == -5
     assert f(A, 8, 6, 16, 2, 3, A, S, V, AK, 0, INFO, ORTH, 1, W, need, NULL) == -3
     assert f(A, 8, 6, 16, 2, 3, U, U, V, AK, 0, INFO, ORTH, 1, W, need, NULL) == -3
+
+
+def test_sparse_svd_validation(lib):
+    need = lib.w_svd_sparse_workspace(8, 6, 16, 2, 3, 1)
+    assert 0 < need < lib.w_svd_workspace(8, 6, 16, 2, 3, 1)   # 8 of 16 slices decomposed
+    assert lib.w_svd_sparse_workspace(8, 6, 16, 0, 3, 1) == 0   # needs L >= 1
+    assert lib.w_svd_sparse_workspace(8, 6, 16, 2, 7, 1) == 0   # k > min(n1, n2)
+    f = lib.w_svd_sparse
+    U, S, V, AK = (ctypes.c_void_p(0x500000), ctypes.c_void_p(0x600000),
+                   ctypes.c_void_p(0x700000), ctypes.c_void_p(0x800000))
+    INFO, ORTH = ctypes.c_void_p(0x900000), ctypes.c_void_p(0xA00000)
+    W = ctypes.c_void_p(0x10000000)
+    assert f(A, 8, 6, 16, 0, 3, U, S, V, AK, 0, INFO, ORTH, 1, W, need, NULL) == -1
+    assert f(A, 8, 6, 12, 3, 3, U, S, V, AK, 0, INFO, ORTH, 1, W, need, NULL) == -1
+    assert f(A, 8, 6, 16, 2, 3, U, S, V, AK, 0, INFO, ORTH, 2, W, need, NULL) == -4
+    assert f(A, 8, 6, 16, 2, 3, NULL, S, V, AK, 0, INFO, ORTH, 1, W, need, NULL) == -2
+    assert f(A, 8, 6, 16, 2, 3, U, S, V, AK, 0, INFO, ORTH, 1, W, need - 1, NULL) == -5
+    # uhat holds 8 slices * 8 * 3 floats = 768 bytes; shat inside it is an alias.
+    assert f(A, 8, 6, 16, 2, 3, U, ctypes.c_void_p(0x500000 + 764), V, AK, 0, INFO, ORTH, 1, W,
+             need, NULL) == -3
 
 
 def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):

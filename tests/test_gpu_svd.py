@@ -122,3 +122,57 @@ def test_f32_shapes(wp, shape, k):
     # approximation is determined to about the FP32 rounding of the data.
     assert rel_fro(host(res.ak), ak_ref) <= 1e-4
     assert host(res.orth_err).max() <= 1e-4
+
+
+# ---- sp-w-svd (Sec. IV-B): only s_L and d_L are decomposed ---------------------
+
+@pytest.mark.parametrize("shape,L,k", [((32, 20, 14), 3, 5), ((16, 7, 9), 4, 3),
+                                       ((8, 65, 40), 1, 3), ((24, 33, 30), 3, 30),
+                                       ((64, 130, 100), 2, 10)])
+def test_sparse_f64_shapes(wp, shape, L, k):
+    import torch
+    p, n1, n2 = shape
+    a = np.random.default_rng(7 * n1 + n2).standard_normal(shape)
+    res = wp.w_svd_sparse(to_dev(a, torch.float64), L, k)
+    torch.cuda.synchronize()
+    nk = 2 * (p >> L)
+    assert res.uhat.shape == (nk, n1, k) and res.shat.shape == (nk, k)
+    assert host(res.info).min() > 0
+    uh_ref, sh_ref, vh_ref, ak_ref = orc.w_svd_sparse(a, L, k)
+    assert rel_fro(host(res.shat), sh_ref) <= 1e-12
+    ak = host(res.ak)
+    assert rel_fro(ak, ak_ref) <= 1e-10
+    assert host(res.orth_err).max() <= 1e-13
+    _check_factors(res, orc.lift_fwd(a, L)[:nk], k, 1e-10)
+    # the finer details of the rebuilt tensor are absent (up to rounding)
+    if nk < p:
+        assert np.abs(orc.lift_fwd(ak, L)[nk:]).max() <= 1e-12 * np.abs(ak).max()
+
+
+def test_sparse_matches_full_at_one_level(wp):
+    # At L = 1 the kept slices are all slices: both entry points run the same kernels.
+    import torch
+    a = cast(np.random.default_rng(9).standard_normal((16, 48, 40)), np.float32)
+    x = to_dev(a, torch.float32)
+    full = wp.w_svd(x, 1, 6)
+    sp = wp.w_svd_sparse(x, 1, 6)
+    torch.cuda.synchronize()
+    for f, s in zip(full[:5], sp[:5]):
+        assert torch.equal(f, s)
+
+
+def test_sparse_table3_shape_f32(wp):
+    # Table 3 shape: 256x192x96 hyperspectral-like tensor, L = 5 (m = 3, 6 kept
+    # slices), rank 32, FP32.
+    import torch
+    from paper_2601_08228_amd import synth
+    x = cast(synth.hsi_like(256, 192, 96, seed=31), np.float32)
+    res = wp.w_svd_sparse(to_dev(x, torch.float32), 5, 32)
+    torch.cuda.synchronize()
+    assert host(res.info).min() > 0
+    _, sh_ref, _, ak_ref = orc.w_svd_sparse(x, 5, 32)
+    ak = host(res.ak)
+    assert rel_fro(host(res.shat), sh_ref) <= 1e-5
+    assert rel_fro(ak, ak_ref) <= 1e-5
+    assert abs(orc.psnr(x, ak) - orc.psnr(x, ak_ref)) <= 0.01
+    assert host(res.orth_err).max() <= 1e-4

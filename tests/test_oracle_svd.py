@@ -149,3 +149,50 @@ def test_psnr_definition():
     y[0, 0, 0] = 0.1
     # N = 24 samples, squared error 0.01 -> 10 log10(24 / 0.01)
     assert abs(orc.psnr(x, y) - 10 * np.log10(2400.0)) < 1e-12
+
+
+def test_sparse_w_svd_equals_w_svd_at_one_level():
+    # With L = 1 the kept slices s_1 and d_1 are all p coefficients.
+    a = np.random.default_rng(50).standard_normal((8, 6, 5))
+    full = orc.w_svd(a, 1, 3)
+    sp = orc.w_svd_sparse(a, 1, 3)
+    for x, y in zip(full, sp):
+        np.testing.assert_allclose(x, y, atol=1e-13)
+
+
+def test_sparse_w_svd_exact_on_tensors_without_fine_details():
+    # Tubes constant on pairs of slices have d_1 = 0; at L = 2 sp-w-svd then keeps
+    # everything there is, so it equals the full w-svd.
+    rng = np.random.default_rng(51)
+    half = rng.standard_normal((8, 7, 6))
+    a = np.repeat(half, 2, axis=0)            # slices 2q and 2q+1 equal
+    assert not np.any(orc.lift_fwd(a, 2)[8:])  # d_1 occupies slices [p/2, p)
+    _, _, _, ak_full = orc.w_svd(a, 2, 4)
+    _, _, _, ak_sp = orc.w_svd_sparse(a, 2, 4)
+    np.testing.assert_allclose(ak_sp, ak_full, atol=1e-12)
+
+
+def test_sparse_w_svd_error_identity():
+    # ||A - A_k||^2 = sum over kept slices of w_c * (tail singular energy)
+    #                 + sum over dropped slices of w_c * ||Ahat_c||^2.
+    rng = np.random.default_rng(52)
+    p, L, k = 32, 3, 2
+    a = rng.standard_normal((p, 6, 5))
+    _, _, _, ak = orc.w_svd_sparse(a, L, k)
+    ah = orc.lift_fwd(a, L)
+    w = orc.coefficient_weights(p, L)
+    kept = 2 * (p >> L)
+    expect = 0.0
+    for c in range(p):
+        if c < kept:
+            s = np.linalg.svd(ah[c], compute_uv=False)
+            expect += w[c] * np.sum(s[k:] ** 2)
+        else:
+            expect += w[c] * np.sum(ah[c] ** 2)
+    err = np.sum((a - ak) ** 2)
+    assert abs(err - expect) <= 1e-11 * expect
+
+
+def test_sparse_w_svd_rejects_level_zero():
+    with pytest.raises(ValueError):
+        orc.w_svd_sparse(np.zeros((4, 3, 3)), 0, 1)
