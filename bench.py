@@ -14,7 +14,11 @@ flops divided by the w-product part of the step (HIP events on the stream
 the kernels run on).  FP32 and plain BF16 forward+backward are timed beside it
 outside the timed steps.  Prints one JSON line.
 
+With --sp-w-svd it instead compares w-svd and sp-w-svd (Sec. IV-B) on a
+256x192x96 hyperspectral-like cube at L = 5 and prints that JSON line.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--sp-w-svd]
 """
 
 import argparse
@@ -48,6 +52,8 @@ def parse():
                     help="skip the oracle timing leg (used by profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--sp-w-svd", action="store_true",
+                    help="instead of the step: w-svd against sp-w-svd on 256x192x96, L=5")
     return ap.parse_args()
 
 
@@ -106,6 +112,9 @@ def main():
     _lib.load()  # fail loudly if the HIP library is missing
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.sp_w_svd:
+        sparse_report(torch, wp, synth, dev, args)
+        return
 
     a = synth.normal_device((P, N1, N2), 21, dev)
     b = synth.normal_device((P, N2, N3), 22, dev)
@@ -172,33 +181,6 @@ def main():
 
     rel_x3_fp32 = max(rel(c_x3, c32), rel(da_x3, da32), rel(db_x3, db32))
     rel_bf16_fp32 = rel(c16, c32)
-
-    # ---- w-svd vs sp-w-svd (Sec. IV-B), outside the timed steps ----------------
-    def time_call(fn, reps=3):
-        r = fn()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            r = fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps, r
-
-    x_t3 = torch.tensor(synth.hsi_like(T3_N1, T3_N2, T3_P, seed=31), dtype=torch.float32,
-                        device=dev)
-    sparse = {"table3_shape": {"n1": T3_N1, "n2": T3_N2, "p": T3_P, "L": T3_L}, "ranks": {}}
-    for rk in T3_RANKS:
-        full_ms, rf = time_call(lambda: wp.w_svd(x_t3, T3_L, rk))
-        sp_ms, rs = time_call(lambda: wp.w_svd_sparse(x_t3, T3_L, rk))
-        sparse["ranks"][str(rk)] = {
-            "w_svd_ms": round(full_ms, 4), "sp_w_svd_ms": round(sp_ms, 4),
-            "w_svd_converged": bool(rf.info.min().item() > 0),
-            "sp_w_svd_converged": bool(rs.info.min().item() > 0)}
-    sp_step_ms, rs = time_call(lambda: wp.w_svd_sparse(x_hsi, SVD_L, SVD_K, workspace=svd_ws))
-    sparse["step_tensor_sp_w_svd_ms"] = round(sp_step_ms, 4)
-    sparse["step_tensor_sp_w_svd_converged"] = bool(rs.info.min().item() > 0)
 
     if args.copy_calibration:
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -287,12 +269,96 @@ def main():
         "rel_diff_bf16_vs_fp32": rel_bf16_fp32,
         "w_svd_sweeps": [int(info.min()), int(info.max())],
         "w_svd_orth_err": [float(orth[0]), float(orth[1])],
-        "sp_w_svd": sparse,
         "roofline": roof,
         "roofline_kernels": rows,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def sparse_report(torch, wp, synth, dev, args):
+    """w-svd against sp-w-svd (Sec. IV-B) on the Table 3 cube shape, one JSON line.
+
+    256x192x96 hyperspectral-like FP32 tensor, L = 5 (m = 3: sp-w-svd decomposes
+    the 6 slices of s_5 and d_5, w-svd all 96), ranks 2, 8, 32, 64.  Each call
+    is timed with HIP events on the current stream (mean of `--steps` calls
+    after `--warmup`); the FP64 oracle of both is timed on the host for context.
+    """
+    import oracle
+    x = torch.tensor(synth.hsi_like(T3_N1, T3_N2, T3_P, seed=31), dtype=torch.float32,
+                     device=dev)
+    x_h = x.double().cpu().numpy()
+    reps = max(args.steps, 1)
+
+    def time_call(fn):
+        for _ in range(max(args.warmup, 1)):
+            r = fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            r = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, r
+
+    def rel(x_, ref):
+        return float(np.linalg.norm((x_ - ref).ravel()) / np.linalg.norm(ref.ravel()))
+
+    rows, cpu_ms = {}, {}
+    for rk in T3_RANKS:
+        full_ms, rf = time_call(lambda: wp.w_svd(x, T3_L, rk))
+        sp_ms, rs = time_call(lambda: wp.w_svd_sparse(x, T3_L, rk))
+        t0 = time.perf_counter()
+        _, _, _, ak_full = oracle.w_svd(x_h, T3_L, rk)
+        t1 = time.perf_counter()
+        _, _, _, ak_sp = oracle.w_svd_sparse(x_h, T3_L, rk)
+        t2 = time.perf_counter()
+        ak_f = rf.ak.double().cpu().numpy()
+        ak_s = rs.ak.double().cpu().numpy()
+        rows[str(rk)] = {
+            "w_svd_ms": round(full_ms, 4), "sp_w_svd_ms": round(sp_ms, 4),
+            "sp_speedup_vs_w_svd": round(full_ms / sp_ms, 3),
+            "w_svd_sweeps_max": int(rf.info.max().item()),
+            "sp_w_svd_sweeps_max": int(rs.info.max().item()),
+            "converged": bool(rf.info.min().item() > 0 and rs.info.min().item() > 0),
+            "psnr_w_svd_db": round(float(oracle.psnr(x_h, ak_f)), 3),
+            "psnr_sp_w_svd_db": round(float(oracle.psnr(x_h, ak_s)), 3),
+            "rel_err_vs_oracle": {"w_svd_Ak": rel(ak_f, ak_full), "sp_w_svd_Ak": rel(ak_s, ak_sp)},
+        }
+        cpu_ms[str(rk)] = {"w_svd": round((t1 - t0) * 1e3, 1), "sp_w_svd": round((t2 - t1) * 1e3, 1)}
+    line = {
+        "metric": "sp-w-svd and w-svd time (FP32, 256x192x96 hyperspectral-like, L=5)",
+        "value": rows["32"]["sp_w_svd_ms"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": reps,
+        "warmup": args.warmup,
+        "higher_is_better": False,
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sp-w-svd vs w-svd, 256x192x96 hyperspectral-like tensor "
+                               "(12 components, noise 0.01), L=5, ranks 2/8/32/64; value at rank 32",
+                   "n1": T3_N1, "n2": T3_N2, "p": T3_P, "L": T3_L},
+        "ranks": rows,
+        "cpu_baseline": {
+            "value": cpu_ms["32"]["sp_w_svd"], "unit": "ms", "cores": host_threads(),
+            "kind": "oracle",
+            "sample": "FP64 NumPy oracle of the same calls on the whole tensor (ms per call, "
+                      "by rank)",
+            "ms": cpu_ms},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def host_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [1]))
+    except Exception:  # threadpoolctl missing: report the visible cores
+        return int(os.cpu_count())
 
 
 def measured_traffic():
@@ -338,11 +404,7 @@ def cpu_baseline(torch, a, b, g, c_gpu, da_gpu, x_hsi, svd_res):
     t2 = time.perf_counter()
     _, sh_ref, _, ak_ref = oracle.w_svd(x_h, SVD_L, SVD_K)
     t3 = time.perf_counter()
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:  # threadpoolctl missing: report the visible cores
-        threads = os.cpu_count()
+    threads = host_threads()
 
     def rel(x, ref):
         return float(np.linalg.norm((x - ref).ravel()) / np.linalg.norm(ref.ravel()))

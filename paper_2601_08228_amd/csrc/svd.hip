@@ -715,29 +715,65 @@ __global__ __launch_bounds__(256) void recover_kernel(const T* __restrict__ ah, 
     for (int t = threadIdx.x; t < mr; t += 256) Vo[int64_t(t) * k + i] = T(-s_src[t]);
 }
 
-// One Newton-Schulz step of the polar iteration, X <- X (3I - X^T X) / 2,
-// for the recovered factor X (one slice (n, k) row-major per workgroup): the
-// recovery inherits the error of U amplified by sigma_1 / sigma_i, and this
-// step removes its non-orthogonality to second order.  FP64 Gram, k <= 64.
+// Gram matrix G = X^T X (FP64) of one slice X (n x k row-major, k <= 64) for
+// 256 threads: thread t accumulates entries e = t + 256 q (a = e / k, b = e % k)
+// in acc[q]; rows are staged through LDS in blocks of kGramRows as FP64.
+constexpr int kGramRows = 64;
+template <typename T>
+__device__ __forceinline__ void gram_k64(const T* __restrict__ X, int n, int k, double (&acc)[16],
+                                         double* s_blk) {
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0;
+  for (int r0 = 0; r0 < n; r0 += kGramRows) {
+    const int rows = n - r0 < kGramRows ? n - r0 : kGramRows;
+    __syncthreads();
+    for (int e = threadIdx.x; e < rows * k; e += 256) s_blk[e] = double(X[int64_t(r0) * k + e]);
+    __syncthreads();
+    for (int r = 0; r < rows; ++r) {
+      const double* xr = s_blk + r * k;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        if (e < k * k) {
+          const int a = e / k, b = e - a * k;
+          acc[q] = fma(xr[a], xr[b], acc[q]);
+        }
+      }
+    }
+  }
+}
+
+// One Newton-Schulz step of the polar iteration, X <- X (3I - X^T X) / 2 =
+// X - X E / 2 with E = X^T X - I, for the recovered factor X (one slice (n, k)
+// row-major per workgroup): the recovery inherits the error of U amplified by
+// sigma_1 / sigma_i, and this step removes its non-orthogonality to second
+// order.  FP64 Gram, k <= 64; X is staged in LDS (n <= 256 rows for FP32
+// data, 128 for FP64: the register-resident Jacobi's limits).
 template <typename T>
 __global__ __launch_bounds__(256) void polish_kernel(T* __restrict__ x, int n, int k) {
+  constexpr int kRows = sizeof(T) == 8 ? 128 : 256;
   __shared__ double s_e[64 * 64];
+  __shared__ double s_blk[kGramRows * 64];
+  __shared__ T s_xs[kRows * 64];
+  if (n > kRows || k > 64) return;  // the host launches it only within these limits
   T* X = x + int64_t(blockIdx.x) * n * k;
-  for (int e = threadIdx.x; e < k * k; e += 256) {
-    const int a = e / k, b = e % k;
-    double acc = 0;
-    for (int r = 0; r < n; ++r) acc = fma(double(X[int64_t(r) * k + a]), double(X[int64_t(r) * k + b]), acc);
-    s_e[e] = acc - (a == b ? 1.0 : 0.0);
+  double acc[16];
+  gram_k64<T>(X, n, k, acc, s_blk);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    if (e < k * k) s_e[e] = acc[q] - ((e / k) == (e % k) ? 1.0 : 0.0);
   }
+  for (int e = threadIdx.x; e < n * k; e += 256) s_xs[e] = X[e];
   __syncthreads();
-  for (int r = threadIdx.x; r < n; r += 256) {
-    double row[64];
-    for (int i = 0; i < k; ++i) row[i] = double(X[int64_t(r) * k + i]);
-    for (int i = 0; i < k; ++i) {
-      double acc = 0;
-      for (int j = 0; j < k; ++j) acc = fma(row[j], s_e[j * k + i], acc);
-      X[int64_t(r) * k + i] = T(row[i] - 0.5 * acc);
-    }
+  // Entry (r, i): X[r][i] - 0.5 * sum_j X[r][j] E[j][i]; consecutive threads
+  // take consecutive i, so E reads are conflict-free and X reads broadcast.
+  for (int e = threadIdx.x; e < n * k; e += 256) {
+    const int r = e / k, i = e - r * k;
+    const T* xr = s_xs + r * k;
+    double acc2 = 0;
+    for (int j = 0; j < k; ++j) acc2 = fma(double(xr[j]), s_e[j * k + i], acc2);
+    X[e] = T(double(xr[i]) - 0.5 * acc2);
   }
 }
 
@@ -748,13 +784,28 @@ __global__ __launch_bounds__(256) void orth_kernel(const T* __restrict__ x, int 
   const int slice = blockIdx.x;
   const T* X = x + int64_t(slice) * n * k;
   double worst = 0;
-  for (int e = threadIdx.x; e < k * k; e += 256) {
-    const int a = e / k, b = e % k;
-    if (b < a) continue;
-    double acc = 0;
-    for (int r = 0; r < n; ++r) acc = fma(double(X[int64_t(r) * k + a]), double(X[int64_t(r) * k + b]), acc);
-    const double dev = fabs(acc - (a == b ? 1.0 : 0.0));
-    worst = (dev > worst || dev != dev) ? dev : worst;
+  if (k <= 64) {
+    __shared__ double s_blk[kGramRows * 64];
+    double acc[16];
+    gram_k64<T>(X, n, k, acc, s_blk);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      if (e < k * k) {
+        const double dev = fabs(acc[q] - ((e / k) == (e % k) ? 1.0 : 0.0));
+        worst = (dev > worst || dev != dev) ? dev : worst;
+      }
+    }
+  } else {
+    for (int e = threadIdx.x; e < k * k; e += 256) {
+      const int a = e / k, b = e % k;
+      if (b < a) continue;
+      double acc = 0;
+      for (int r = 0; r < n; ++r)
+        acc = fma(double(X[int64_t(r) * k + a]), double(X[int64_t(r) * k + b]), acc);
+      const double dev = fabs(acc - (a == b ? 1.0 : 0.0));
+      worst = (dev > worst || dev != dev) ? dev : worst;
+    }
   }
   __shared__ double red[256];
   red[threadIdx.x] = worst;
