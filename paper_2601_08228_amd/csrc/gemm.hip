@@ -21,9 +21,16 @@
 // registers before the MFMAs of tile t and written to the other stage after
 // them, so one barrier per K-tile suffices.
 //
+// BF16 operands whose dimensions allow whole 16-byte chunks (the common case)
+// take a second kernel, face_bf16_direct, whose copies go from global memory
+// straight into LDS (buffer_load ... lds) through a ring of K stages, with
+// transposed operands read by ds_read_b64_tr_b16; see its description below.
+//
 // Tile order: the hardware deals workgroups round-robin over the 8 XCDs; the
 // linear id is remapped so that consecutive logical tiles - the tiles of one
 // slice, which share A rows and B columns - land on the same XCD and its L2.
+
+#include <type_traits>
 
 #include "wp_internal.h"
 
@@ -36,6 +43,14 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <int N, int I = 0, typename F>
+__device__ __forceinline__ void static_for_n(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for_n<N, I + 1>(f);
+  }
+}
 
 constexpr int kChunksPerRow = 4;  // 64-byte LDS rows
 constexpr int kNumXcd = 8;
@@ -425,6 +440,399 @@ __global__ __launch_bounds__(64 * Cfg::WM * Cfg::WN, 1) void face_gemm_kernel(Ge
     }
 }
 
+// ---- BF16 face-product with direct-to-LDS loads -----------------------------
+// The global -> LDS copies bypass registers (buffer_load ... lds, 16 bytes per
+// lane), so several K stages can be in flight: stage t is consumed while
+// stages t+1 .. t+S-1 load.  Each operand keeps its stored layout in LDS:
+//   * K contiguous in memory ("KC": A not transposed, B transposed): LDS rows
+//     of BK = 16 K values (32 bytes); chunk c (8 values) of row r sits at
+//     chunk c ^ (((r >> 2) ^ (r >> 3)) & 1), so the fragment reads of 8 or 16
+//     consecutive rows cover disjoint banks;
+//   * K slow in memory ("KS"): LDS rows are the 16 K values' rows of 256
+//     elements (512 bytes); chunk c of K-row k sits at c ^ h(k), h(k) = 0, 6,
+//     10, 12 for k mod 4 = 0..3; fragments are read with ds_read_b64_tr_b16,
+//     which hands lane j of each 16-lane group element [k0 + q][r0 + j]
+//     (q = 0..3) when lane i addresses [k0 + i/4][r0 + 4 (i mod 4)].
+// Lanes outside the matrix get an offset past the buffer's end, so the
+// hardware returns zeros for them.
+namespace dl {
+constexpr int BM = 256, BN = 256, BK = 16, TM = 32;
+constexpr int WN = 4, MT = 4, NT = 2;
+constexpr int THREADS = 512;
+constexpr int PLANE = 256 * BK * 2;  // bytes of one operand plane of one stage
+constexpr uint32_t kOut = 0x80000000u;  // buffer offset that reads as zero
+}  // namespace dl
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_t;
+
+__device__ __forceinline__ int kc_chunk(int row, int c) { return c ^ (((row >> 2) ^ (row >> 3)) & 1); }
+__device__ __forceinline__ int ks_h(int k) { return (0x0C0A0600 >> (8 * (k & 3))) & 0xFF; }
+
+// s_waitcnt with only the vector-memory counter limited to n (gfx9 encoding:
+// vmcnt in bits 3:0 and 15:14, expcnt and lgkmcnt left at their maxima).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  __builtin_amdgcn_s_waitcnt((N & 15) | (((N >> 4) & 3) << 14) | (7 << 4) | (15 << 8));
+}
+// Wait until at most `stages` stages of LPS loads each are pending (stages <= S - 2).
+template <int S, int LPS>
+__device__ __forceinline__ void wait_stages(int stages) {
+  static_for_n<S - 1>([&](auto I) {
+    constexpr int P = decltype(I)::value;
+    if (stages == P) wait_vm<P * LPS>();
+  });
+}
+
+// 32-bit LDS address of a pointer into a __shared__ array.
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return static_cast<uint32_t>(
+      reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) char*)p));
+}
+
+// Per-lane source geometry of one operand plane (see the layouts above).
+struct DlSrc {
+  __amdgpu_buffer_rsrc_t rsrc;
+  uint32_t base;     // byte offset of this lane's chunk at k0 = 0
+  uint32_t kstep;    // bytes per K element of k0
+  int kidx;          // K index of this lane's chunk relative to k0 (KC: 8c, KS: k)
+  bool rok;          // the lane's rows / columns are inside the matrix
+};
+
+template <bool KC>
+__device__ __forceinline__ DlSrc dl_src(const uint16_t* plane, int64_t ld, int r0, int rtot,
+                                        int kk) {
+  DlSrc d;
+  const int t = threadIdx.x;
+  if constexpr (KC) {
+    const int r = t >> 1;
+    const int c = kc_chunk(r, t & 1);
+    d.base = uint32_t(((int64_t(r0) + r) * ld + 8 * c) * 2);
+    d.kstep = 2;
+    d.kidx = 8 * c;
+    d.rok = r0 + r < rtot;
+    d.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(plane), 0,
+                                               int(int64_t(rtot) * ld * 2), 0x00020000);
+  } else {
+    const int k = t >> 5;
+    const int c = (t & 31) ^ ks_h(k);
+    d.base = uint32_t((int64_t(k) * ld + r0 + 8 * c) * 2);
+    d.kstep = uint32_t(ld * 2);
+    d.kidx = k;
+    d.rok = r0 + 8 * c < rtot;
+    d.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(plane), 0,
+                                               int(int64_t(kk) * ld * 2), 0x00020000);
+  }
+  return d;
+}
+
+__device__ __forceinline__ void dl_issue(const DlSrc& d, char* lds_plane, int k0, int kk) {
+  const bool ok = d.rok && (k0 + d.kidx < kk);
+  const uint32_t off = ok ? d.base + uint32_t(k0) * d.kstep : dl::kOut;
+  // Each wavefront fills 1 KiB of the plane: lane l writes bytes 16 l of it.
+  // (The pointer stays derived from the stage buffer, so the compiler knows
+  // which LDS object the copy writes.)
+  const int wave_off = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x & ~63) * 16);
+  __attribute__((address_space(3))) char* dst = (__attribute__((address_space(3))) char*)lds_plane;
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(d.rsrc, (lds_t*)(dst + wave_off), 16, off, 0, 0, 0);
+}
+
+// ---- fragment reads ----------------------------------------------------------
+// The LDS reads of a stage are written as inline assembly, each block ending
+// with its own lgkmcnt(0) wait: the compiler cannot tell which LDS object a
+// buffer-to-LDS copy writes, so for reads it can see it would wait for every
+// copy in flight (vmcnt(0)), which would undo the multi-stage pipeline.  The
+// copies a stage depends on are waited for explicitly before the barrier.
+
+// Per-lane byte offset, inside a stage buffer, of the lane's 16-byte K-chunk of
+// tile row xb + (l & 31) in a K-contiguous plane (MFMA operand layout: K
+// values 8 (l >> 5) .. +7).  Tiles 32 rows apart differ by 1024 bytes.
+__device__ __forceinline__ uint32_t kc_lane_off() {
+  const int l = threadIdx.x & 63;
+  const int row = l & 31;
+  return uint32_t(row * (dl::BK * 2) + 16 * kc_chunk(row, l >> 5));
+}
+
+// Per-lane byte offset of a K-slow plane's transposed read: lane i of 16-lane
+// group g addresses K-row 8 (g >> 1) + 4 half + i / 4, columns
+// xb + 16 (g & 1) + 4 (i mod 4) .. +3.
+__device__ __forceinline__ uint32_t ks_lane_off(int xb, int half) {
+  const int l = threadIdx.x & 63;
+  const int g = l >> 4, i = l & 15;
+  const int r = xb + 16 * (g & 1) + 4 * (i & 3);
+  const int k = 8 * (g >> 1) + 4 * half + (i >> 2);
+  return uint32_t(k * (dl::BM * 2) + 16 * ((r >> 3) ^ ks_h(k)) + 8 * (i & 1));
+}
+
+#define WP_KC2 "ds_read_b128 %0, %4\n\tds_read_b128 %1, %4 offset:1024\n\t"
+// K-contiguous fragments: T tiles (32 rows apart) of NPL planes (8 KiB apart).
+template <int T, int NPL>
+__device__ __forceinline__ void kc_frags(uint32_t a, u32x4 (&f)[T * NPL]) {
+  if constexpr (T == 2 && NPL == 1) {
+    asm volatile("ds_read_b128 %0, %2\n\tds_read_b128 %1, %2 offset:1024\n\ts_waitcnt lgkmcnt(0)"
+                 : "=v"(f[0]), "=v"(f[1]) : "v"(a) : "memory");
+  } else if constexpr (T == 2 && NPL == 2) {
+    asm volatile("ds_read_b128 %0, %4\n\tds_read_b128 %1, %4 offset:1024\n\t"
+                 "ds_read_b128 %2, %4 offset:8192\n\tds_read_b128 %3, %4 offset:9216\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=v"(f[0]), "=v"(f[1]), "=v"(f[2]), "=v"(f[3]) : "v"(a) : "memory");
+  } else if constexpr (T == 4 && NPL == 1) {
+    asm volatile("ds_read_b128 %0, %4\n\tds_read_b128 %1, %4 offset:1024\n\t"
+                 "ds_read_b128 %2, %4 offset:2048\n\tds_read_b128 %3, %4 offset:3072\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=v"(f[0]), "=v"(f[1]), "=v"(f[2]), "=v"(f[3]) : "v"(a) : "memory");
+  } else {
+    static_assert(T == 4 && NPL == 2, "unsupported fragment count");
+    asm volatile("ds_read_b128 %0, %8\n\tds_read_b128 %1, %8 offset:1024\n\t"
+                 "ds_read_b128 %2, %8 offset:2048\n\tds_read_b128 %3, %8 offset:3072\n\t"
+                 "ds_read_b128 %4, %8 offset:8192\n\tds_read_b128 %5, %8 offset:9216\n\t"
+                 "ds_read_b128 %6, %8 offset:10240\n\tds_read_b128 %7, %8 offset:11264\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=v"(f[0]), "=v"(f[1]), "=v"(f[2]), "=v"(f[3]), "=v"(f[4]), "=v"(f[5]),
+                   "=v"(f[6]), "=v"(f[7])
+                 : "v"(a) : "memory");
+  }
+}
+#undef WP_KC2
+
+// K-slow fragments by transposed reads: addresses ad[2 t + half] for tile t,
+// plane p at + 8 KiB p; output h[(p T + t) 2 + half] holds 4 K values.
+template <int T, int NPL>
+__device__ __forceinline__ void ks_frags(const uint32_t (&ad)[2 * T], u32x2 (&h)[2 * T * NPL]) {
+  if constexpr (T == 2 && NPL == 1) {
+    asm volatile("ds_read_b64_tr_b16 %0, %4\n\tds_read_b64_tr_b16 %1, %5\n\t"
+                 "ds_read_b64_tr_b16 %2, %6\n\tds_read_b64_tr_b16 %3, %7\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=v"(h[0]), "=v"(h[1]), "=v"(h[2]), "=v"(h[3])
+                 : "v"(ad[0]), "v"(ad[1]), "v"(ad[2]), "v"(ad[3]) : "memory");
+  } else if constexpr (T == 2 && NPL == 2) {
+    asm volatile("ds_read_b64_tr_b16 %0, %8\n\tds_read_b64_tr_b16 %1, %9\n\t"
+                 "ds_read_b64_tr_b16 %2, %10\n\tds_read_b64_tr_b16 %3, %11\n\t"
+                 "ds_read_b64_tr_b16 %4, %8 offset:8192\n\tds_read_b64_tr_b16 %5, %9 offset:8192\n\t"
+                 "ds_read_b64_tr_b16 %6, %10 offset:8192\n\tds_read_b64_tr_b16 %7, %11 offset:8192\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=v"(h[0]), "=v"(h[1]), "=v"(h[2]), "=v"(h[3]), "=v"(h[4]), "=v"(h[5]),
+                   "=v"(h[6]), "=v"(h[7])
+                 : "v"(ad[0]), "v"(ad[1]), "v"(ad[2]), "v"(ad[3]) : "memory");
+  } else if constexpr (T == 4 && NPL == 1) {
+    asm volatile("ds_read_b64_tr_b16 %0, %8\n\tds_read_b64_tr_b16 %1, %9\n\t"
+                 "ds_read_b64_tr_b16 %2, %10\n\tds_read_b64_tr_b16 %3, %11\n\t"
+                 "ds_read_b64_tr_b16 %4, %12\n\tds_read_b64_tr_b16 %5, %13\n\t"
+                 "ds_read_b64_tr_b16 %6, %14\n\tds_read_b64_tr_b16 %7, %15\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=v"(h[0]), "=v"(h[1]), "=v"(h[2]), "=v"(h[3]), "=v"(h[4]), "=v"(h[5]),
+                   "=v"(h[6]), "=v"(h[7])
+                 : "v"(ad[0]), "v"(ad[1]), "v"(ad[2]), "v"(ad[3]), "v"(ad[4]), "v"(ad[5]),
+                   "v"(ad[6]), "v"(ad[7]) : "memory");
+  } else {
+    static_assert(T == 4 && NPL == 2, "unsupported fragment count");
+    asm volatile("ds_read_b64_tr_b16 %0, %16\n\tds_read_b64_tr_b16 %1, %17\n\t"
+                 "ds_read_b64_tr_b16 %2, %18\n\tds_read_b64_tr_b16 %3, %19\n\t"
+                 "ds_read_b64_tr_b16 %4, %20\n\tds_read_b64_tr_b16 %5, %21\n\t"
+                 "ds_read_b64_tr_b16 %6, %22\n\tds_read_b64_tr_b16 %7, %23\n\t"
+                 "ds_read_b64_tr_b16 %8, %16 offset:8192\n\tds_read_b64_tr_b16 %9, %17 offset:8192\n\t"
+                 "ds_read_b64_tr_b16 %10, %18 offset:8192\n\tds_read_b64_tr_b16 %11, %19 offset:8192\n\t"
+                 "ds_read_b64_tr_b16 %12, %20 offset:8192\n\tds_read_b64_tr_b16 %13, %21 offset:8192\n\t"
+                 "ds_read_b64_tr_b16 %14, %22 offset:8192\n\tds_read_b64_tr_b16 %15, %23 offset:8192\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=v"(h[0]), "=v"(h[1]), "=v"(h[2]), "=v"(h[3]), "=v"(h[4]), "=v"(h[5]),
+                   "=v"(h[6]), "=v"(h[7]), "=v"(h[8]), "=v"(h[9]), "=v"(h[10]), "=v"(h[11]),
+                   "=v"(h[12]), "=v"(h[13]), "=v"(h[14]), "=v"(h[15])
+                 : "v"(ad[0]), "v"(ad[1]), "v"(ad[2]), "v"(ad[3]), "v"(ad[4]), "v"(ad[5]),
+                   "v"(ad[6]), "v"(ad[7]) : "memory");
+  }
+}
+
+// All fragments of one operand for one stage: T tiles of NPL planes, tile t of
+// plane p in f[p T + t].  KC: lane_off = kc_lane_off(); KS: ks_off[2 t + half]
+// = ks_lane_off(xb + 32 t, half).
+template <bool KC, int T, int NPL>
+__device__ __forceinline__ void stage_frags(uint32_t buf, uint32_t kc_off, const uint32_t (&ks_off)[2 * T],
+                                            u32x4 (&f)[T * NPL]) {
+  if constexpr (KC) {
+    kc_frags<T, NPL>(buf + kc_off, f);
+  } else {
+    uint32_t ad[2 * T];
+#pragma unroll
+    for (int q = 0; q < 2 * T; ++q) ad[q] = buf + ks_off[q];
+    u32x2 h[2 * T * NPL];
+    ks_frags<T, NPL>(ad, h);
+#pragma unroll
+    for (int q = 0; q < T * NPL; ++q) {
+      f[q][0] = h[2 * q][0];
+      f[q][1] = h[2 * q][1];
+      f[q][2] = h[2 * q + 1][0];
+      f[q][3] = h[2 * q + 1][1];
+    }
+  }
+}
+
+// One LDS stage buffer per B: separate __shared__ objects, so that the
+// compiler can tell the copies into one stage from the reads of another and
+// only waits for the copies a read depends on.
+template <int B, int BYTES>
+__device__ __forceinline__ char* dl_stage() {
+  __shared__ __align__(16) char buf[BYTES];
+  return buf;
+}
+
+// Workgroup barrier without a memory fence: the waits for the copies are
+// explicit, and the signal fences keep the compiler from moving LDS accesses
+// across it.
+__device__ __forceinline__ void dl_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+template <bool TA, bool TB, bool X3, int S>
+__global__ __launch_bounds__(dl::THREADS, 1) void face_bf16_direct(GemmArgs args) {
+  using namespace dl;
+  constexpr int NPL = X3 ? 2 : 1;
+  constexpr int STAGE = 2 * NPL * PLANE;
+  constexpr bool A_KC = !TA, B_KC = TB;
+
+  const int64_t tiles_per_slice = int64_t(args.tiles_m) * args.tiles_n;
+  const int64_t total = tiles_per_slice * args.batch;
+  const int64_t logical = xcd_remap(blockIdx.x, total);
+  const int64_t slice = logical / tiles_per_slice;
+  const int64_t t_in = logical % tiles_per_slice;
+  const int m0 = int(t_in / args.tiles_n) * BM;
+  const int n0 = int(t_in % args.tiles_n) * BN;
+  const int kk = args.k;
+
+  const uint16_t* pa[2] = {static_cast<const uint16_t*>(args.a_hi) + slice * args.sa,
+                           X3 ? static_cast<const uint16_t*>(args.a_lo) + slice * args.sa : nullptr};
+  const uint16_t* pb[2] = {static_cast<const uint16_t*>(args.b_hi) + slice * args.sb,
+                           X3 ? static_cast<const uint16_t*>(args.b_lo) + slice * args.sb : nullptr};
+  DlSrc sa[NPL], sb[NPL];
+#pragma unroll
+  for (int q = 0; q < NPL; ++q) {
+    sa[q] = dl_src<A_KC>(pa[q], args.lda, m0, args.m, kk);
+    sb[q] = dl_src<B_KC>(pb[q], args.ldb, n0, args.n, kk);
+  }
+  // Copies of K stage st into stage buffer B.
+  auto issue = [&](auto BB, int st) {
+    char* base = dl_stage<decltype(BB)::value, STAGE>();
+#pragma unroll
+    for (int q = 0; q < NPL; ++q) {
+      dl_issue(sa[q], base + q * PLANE, st * BK, kk);
+      dl_issue(sb[q], base + (NPL + q) * PLANE, st * BK, kk);
+    }
+  };
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = (wave / WN) * (MT * TM);
+  const int wn = (wave % WN) * (NT * TM);
+  const int lrow = lane % TM;
+  const int lgrp = lane / TM;
+
+  f32x16 acc[MT][NT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0;
+
+  // Per-lane fragment offsets inside a stage plane (tiles 32 rows apart are
+  // 1 KiB apart in a K-contiguous plane).
+  const uint32_t a_kc_off = uint32_t(wm * BK * 2) + kc_lane_off();
+  const uint32_t b_kc_off = uint32_t(wn * BK * 2) + kc_lane_off();
+  uint32_t a_ks_off[2 * MT], b_ks_off[2 * NT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) a_ks_off[2 * t + h] = ks_lane_off(wm + 32 * t, h);
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) b_ks_off[2 * t + h] = ks_lane_off(wn + 32 * t, h);
+
+  const int nk = (kk + BK - 1) / BK;
+  static_for_n<S - 1>([&](auto BB) {
+    if (decltype(BB)::value < nk) issue(BB, decltype(BB)::value);
+  });
+
+  // K stage t lives in buffer t mod S; the loop is unrolled S times so that
+  // every buffer index is a constant.
+  for (int t0 = 0; t0 < nk; t0 += S) {
+    static_for_n<S>([&](auto UU) {
+      constexpr int u = decltype(UU)::value;
+      const int t = t0 + u;
+      if (t >= nk) return;
+      // Stage t has landed once at most the stages issued after it are pending.
+      const int pending = (nk - 1 < t + S - 2 ? nk - 1 : t + S - 2) - t;
+      wait_stages<S, 2 * NPL>(pending);
+      dl_barrier();  // every wave's copies of stage t are in LDS; stage t-1 is consumed
+      if (t + S - 1 < nk) issue(std::integral_constant<int, (u + S - 1) % S>{}, t + S - 1);
+
+      const uint32_t buf = lds_addr(dl_stage<u, STAGE>());
+      u32x4 fa[MT * NPL], fb[NT * NPL];
+      stage_frags<B_KC, NT, NPL>(buf + NPL * PLANE, b_kc_off, b_ks_off, fb);
+      stage_frags<A_KC, MT, NPL>(buf, a_kc_off, a_ks_off, fa);
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          if constexpr (X3) {
+            mma_bf16(fa[MT + i], fb[j], acc[i][j]);
+            mma_bf16(fa[i], fb[NT + j], acc[i][j]);
+          }
+          mma_bf16(fa[i], fb[j], acc[i][j]);
+        }
+    });
+  }
+
+  float* cbase = static_cast<float*>(args.c) + slice * args.sc;
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const int col = n0 + wn + j * TM + lrow;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = m0 + wm + i * TM + (r / 4) * 8 + lgrp * 4 + (r % 4);
+        if (row < args.m && col < args.n) cbase[int64_t(row) * args.ldc + col] = acc[i][j][r];
+      }
+    }
+}
+
+template <bool TA, bool TB, bool X3, int S>
+hipError_t launch_direct(const GemmArgs& a0, hipStream_t s) {
+  GemmArgs a = a0;
+  a.tiles_m = int((a.m + dl::BM - 1) / dl::BM);
+  a.tiles_n = int((a.n + dl::BN - 1) / dl::BN);
+  const int64_t total = int64_t(a.tiles_m) * a.tiles_n * a.batch;
+  if (total == 0) return hipSuccess;
+  if (total > 0x7fffffff) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((face_bf16_direct<TA, TB, X3, S>), dim3(unsigned(total)), dim3(dl::THREADS),
+                     0, s, a);
+  return hipGetLastError();
+}
+
+// The direct path needs whole 16-byte chunks everywhere: K and every
+// K-slow operand's other dimension multiples of 8, 16-byte aligned rows, and
+// slices addressable with 32-bit buffer offsets.
+inline bool direct_ok(const GemmArgs& a, bool ta, bool tb) {
+  if (!a.vec_a || !a.vec_b || a.k % 8 != 0) return false;
+  if (ta && a.m % 8 != 0) return false;
+  if (!tb && a.n % 8 != 0) return false;
+  const int64_t abytes = int64_t(ta ? a.k : a.m) * a.lda * 2;
+  const int64_t bbytes = int64_t(tb ? a.n : a.k) * a.ldb * 2;
+  return abytes < (int64_t(1) << 31) && bbytes < (int64_t(1) << 31);
+}
+
+template <bool X3>
+hipError_t dispatch_direct(const GemmArgs& a, bool ta, bool tb, hipStream_t s) {
+  constexpr int S = X3 ? 4 : 8;
+  if (!ta && !tb) return launch_direct<false, false, X3, S>(a, s);
+  if (ta && !tb) return launch_direct<true, false, X3, S>(a, s);
+  if (!ta && tb) return launch_direct<false, true, X3, S>(a, s);
+  return launch_direct<true, true, X3, S>(a, s);
+}
+
 template <class Cfg, bool TA, bool TB, bool X3>
 hipError_t launch_cfg(const GemmArgs& a0, hipStream_t s) {
   using D = Dims<Cfg>;
@@ -502,6 +910,8 @@ hipError_t launch_face_bf16(const uint16_t* ahi, const uint16_t* alo, const uint
                             int64_t batch, bool ta, bool tb, bool x3, hipStream_t s) {
   const GemmArgs a = make_args<CfgBF16>(ahi, x3 ? alo : nullptr, bhi, x3 ? blo : nullptr, c, m, kk,
                                         n, batch, ta, tb);
+  if (direct_ok(a, ta, tb))
+    return x3 ? dispatch_direct<true>(a, ta, tb, s) : dispatch_direct<false>(a, ta, tb, s);
   return x3 ? dispatch<CfgBF16, true>(a, ta, tb, s) : dispatch<CfgBF16, false>(a, ta, tb, s);
 }
 

@@ -25,9 +25,13 @@ def _operands(p, m, k, n, ta, tb, seed, dist="normal"):
 
 
 # (p, m, k, n): several tiles plus ragged tails in every dimension, single-tile,
-# degenerate 1-wide dimensions, and K shorter than one K-tile.
+# degenerate 1-wide dimensions, and K shorter than one K-tile.  The last two
+# have every dimension a multiple of 8, so the BF16 modes take the
+# direct-to-LDS kernel in all four transpose combinations (tails of 8 rows
+# and columns, K not a multiple of the 16-wide stage, many stages).
 SHAPES = [(3, 130, 70, 200), (2, 64, 64, 64), (1, 1, 1, 1), (5, 17, 3, 9), (4, 257, 33, 129),
-          (2, 300, 520, 260), (16, 32, 24, 20), (1, 7, 1000, 5)]
+          (2, 300, 520, 260), (16, 32, 24, 20), (1, 7, 1000, 5), (2, 264, 200, 328),
+          (1, 512, 1032, 256)]
 TRANS = [(False, False), (True, False), (False, True), (True, True)]
 
 
