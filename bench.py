@@ -54,6 +54,12 @@ def parse():
                     help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--sp-w-svd", action="store_true",
                     help="instead of the step: w-svd against sp-w-svd on 256x192x96, L=5")
+    ap.add_argument("--table1", action="store_true",
+                    help="instead of the step: w-product of p x p x p tensors, p = 2 .. 1024 "
+                         "(the shapes of the paper's Table 1), L = log2 p")
+    ap.add_argument("--configs", action="store_true",
+                    help="instead of the step: the other workloads (FP64 small case, config-3 "
+                         "PSNR, 1024x1024x128 precision modes, 50-step deblurring solve)")
     return ap.parse_args()
 
 
@@ -114,6 +120,12 @@ def main():
     torch.cuda.set_device(dev)
     if args.sp_w_svd:
         sparse_report(torch, wp, synth, dev, args)
+        return
+    if args.configs:
+        configs_report(torch, wp, synth, dev, args)
+        return
+    if args.table1:
+        table1_report(torch, wp, dev, args)
         return
 
     a = synth.normal_device((P, N1, N2), 21, dev)
@@ -349,6 +361,221 @@ def sparse_report(torch, wp, synth, dev, args):
             "sample": "FP64 NumPy oracle of the same calls on the whole tensor (ms per call, "
                       "by rank)",
             "ms": cpu_ms},
+    }
+    print(json.dumps(line), flush=True)
+
+
+# The paper's Table 1 w-product times (seconds, CPU, mean of 10 runs), p = 2^1 .. 2^10.
+PAPER_TABLE1_W_S = [1.576734e-04, 1.577830e-04, 3.587484e-04, 4.789996e-04, 1.763617e-03,
+                    8.662295e-03, 5.306451e-02, 3.919755e-01, 3.161437e+00, 7.749125e+01]
+
+
+def table1_report(torch, wp, dev, args):
+    """w-product of A, B in R^{p x p x p}, U[0,1) entries, p = 2^1 .. 2^10, L = log2 p
+    (the worst case the paper names for Table 1), FP32 and bf16x3 face-products.
+    Each call (one library call: both liftings, the face-products, the inverse) is
+    timed with HIP events, mean of `--steps` calls after one warm-up; for p <= 256
+    the FP32 result is checked against the FP64 oracle.
+    """
+    import oracle
+    rows = []
+    for e in range(1, 11):
+        p = 1 << e
+        g = torch.Generator(device=dev)
+        g.manual_seed(1000 + e)
+        a = torch.rand((p, p, p), generator=g, device=dev)
+        b = torch.rand((p, p, p), generator=g, device=dev)
+        row = {"p": p, "L": e, "paper_cpu_w_product_s": PAPER_TABLE1_W_S[e - 1]}
+        for gemm in ("native", "bf16x3"):
+            ws = torch.empty(max(wp.w_product_workspace(p, p, p, p, e, torch.float32, gemm), 1),
+                             dtype=torch.uint8, device=dev)
+            c = torch.empty_like(a)
+            wp.w_product(a, b, e, gemm=gemm, out=c, workspace=ws)
+            torch.cuda.synchronize()
+            reps = max(args.steps, 1)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                wp.w_product(a, b, e, gemm=gemm, out=c, workspace=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            key = "fp32" if gemm == "native" else "bf16x3"
+            row[key + "_ms"] = round(ms, 5)
+            row[key + "_effective_tflops"] = round(2.0 * p ** 4 / (ms * 1e-3) / 1e12, 4)
+            if gemm == "native":
+                row["speedup_vs_paper_cpu"] = round(PAPER_TABLE1_W_S[e - 1] / (ms * 1e-3), 1)
+                if p <= 256:
+                    ref = oracle.w_product(a.double().cpu().numpy(), b.double().cpu().numpy(), e)
+                    got = c.double().cpu().numpy()
+                    row["fp32_rel_err_vs_oracle"] = float(np.linalg.norm((got - ref).ravel())
+                                                          / np.linalg.norm(ref.ravel()))
+            del ws, c
+        rows.append(row)
+        del a, b
+        torch.cuda.empty_cache()
+    line = {
+        "metric": "w-product time of p x p x p tensors (the shapes of Table 1), L = log2 p",
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": max(args.steps, 1),
+        "higher_is_better": False,
+        "vs_baseline": None,
+        "data": "synthetic U[0,1)",
+        "config": {"workload": "w-product A *_w B, A, B p x p x p, p = 2..1024, L = log2 p, "
+                               "FP32 and bf16x3 face-products"},
+        "rows": rows,
+        "note": "paper_cpu_w_product_s is the paper's own CPU timing (other hardware), context only",
+    }
+    print(json.dumps(line), flush=True)
+
+
+def configs_report(torch, wp, synth, dev, args):
+    """The workloads beside the step, one JSON line (GPU timed with HIP events).
+
+    * FP64 32x24x16 . 24x20x16, L=2: w-product and full-rank w-svd latency and
+      errors; the oracle timed as the median of 20 calls, on all host threads
+      and on one.
+    * 256x256x192 hyperspectral-like tensor, L=3, k=20: PSNR of A_20 from the GPU
+      and from the oracle.
+    * 1024x1024x128 U(-1,1), L=3: w-product per face-product mode, against the
+      whole FP64 oracle product.
+    * Deblurring 256x256x128, L=3: 50 gradient steps through the adjoint (FP32
+      and bf16x3 face-products), against the oracle trajectory.
+    """
+    import statistics
+    import oracle
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # threadpoolctl missing: no one-thread figure
+        threadpool_limits = None
+
+    def ev_ms(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        return statistics.median(times)
+
+    def host_ms(fn, reps):
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            times.append((time.perf_counter() - t0) * 1e3)
+        return statistics.median(times)
+
+    def rel(x_, ref):
+        return float(np.linalg.norm((np.asarray(x_, np.float64) - ref).ravel())
+                     / np.linalg.norm(ref.ravel()))
+
+    out = {}
+    # FP64 small case
+    a = synth.normal((16, 32, 24), seed=1)
+    b = synth.normal((16, 24, 20), seed=2)
+    ta = torch.tensor(a, device=dev)
+    tb = torch.tensor(b, device=dev)
+    c = wp.w_product(ta, tb, 2)
+    res = wp.w_svd(ta, 2, 24)
+    torch.cuda.synchronize()
+    c_ref = oracle.w_product(a, b, 2)
+    _, sh_ref, _, _ = oracle.w_svd(a, 2, 24)
+    row = {
+        "w_product_ms": round(ev_ms(lambda: wp.w_product(ta, tb, 2), 50), 4),
+        "w_svd_ms": round(ev_ms(lambda: wp.w_svd(ta, 2, 24), 20), 4),
+        "rel_err_C": rel(c.cpu().numpy(), c_ref),
+        "rel_err_A_vs_U_S_Vt": rel(res.ak.cpu().numpy(), a),
+        "rel_err_shat": rel(res.shat.cpu().numpy(), sh_ref),
+        "orth_err": [float(v) for v in res.orth_err.cpu()],
+        "oracle_w_product_ms": round(host_ms(lambda: oracle.w_product(a, b, 2), 20), 3),
+        "oracle_w_svd_ms": round(host_ms(lambda: oracle.w_svd(a, 2, 24), 20), 3),
+        "oracle_threads": host_threads(),
+    }
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            row["oracle_w_product_ms_1_thread"] = round(host_ms(lambda: oracle.w_product(a, b, 2), 20), 3)
+            row["oracle_w_svd_ms_1_thread"] = round(host_ms(lambda: oracle.w_svd(a, 2, 24), 20), 3)
+    out["fp64_32x24x16_L2"] = row
+
+    # config-3 PSNR
+    x = synth.hsi_like(SVD_N, SVD_N, SVD_P, seed=3)
+    x32 = x.astype(np.float32)
+    res = wp.w_svd(torch.tensor(x32, device=dev), SVD_L, SVD_K)
+    ak = res.ak.double().cpu().numpy()
+    _, _, _, ak_ref = oracle.w_svd(x32.astype(np.float64), SVD_L, SVD_K)
+    out["w_svd_256x256x192_L3_k20"] = {
+        "psnr_gpu_db": round(float(oracle.psnr(x32, ak)), 4),
+        "psnr_oracle_db": round(float(oracle.psnr(x32, ak_ref)), 4),
+        "rel_err_Ak": rel(ak, ak_ref),
+    }
+
+    # precision modes at 1024x1024x128
+    a = synth.uniform_device((128, 1024, 1024), 41, dev)
+    b = synth.uniform_device((128, 1024, 1024), 42, dev)
+    t0 = time.perf_counter()
+    c_ref = oracle.w_product(a.double().cpu().numpy(), b.double().cpu().numpy(), 3)
+    oracle_s = time.perf_counter() - t0
+    flops = 2.0 * 1024 ** 3 * 128
+    modes = {}
+    for gemm in ("native", "bf16x3", "bf16"):
+        ws = torch.empty(wp.w_product_workspace(1024, 1024, 1024, 128, 3, torch.float32, gemm),
+                         dtype=torch.uint8, device=dev)
+        cc = torch.empty((128, 1024, 1024), dtype=torch.float32, device=dev)
+        ms = ev_ms(lambda: wp.w_product(a, b, 3, gemm=gemm, out=cc, workspace=ws), 10)
+        modes["fp32" if gemm == "native" else gemm] = {
+            "ms": round(ms, 4), "effective_tflops": round(flops / (ms * 1e-3) / 1e12, 2),
+            "rel_err_vs_oracle": rel(cc.cpu().numpy(), c_ref)}
+        del ws, cc
+    out["w_product_1024x1024x128_L3"] = {"modes": modes, "oracle_s": round(oracle_s, 2)}
+    del a, b, c_ref
+    torch.cuda.empty_cache()
+
+    # deblurring solve
+    from paper_2601_08228_amd import deblur
+    n, p, L, steps = 256, 128, 3, 50
+    g = synth.gaussian_band(n)
+    k = synth.stack_slices(g, p).astype(np.float32)
+    xt = synth.hsi_like(n, n, p, seed=5)
+    noise = synth.normal((p, n, n), seed=105, scale=0.01)
+    y = (oracle.w_product(k, xt, L) + noise).astype(np.float32)
+    eta = 1.0 / (2.0 * np.linalg.norm(g, 2) ** 2)
+    t0 = time.perf_counter()
+    x_ref, loss_ref = oracle.deblur_gd(k, y, L, steps, eta)
+    oracle_s = time.perf_counter() - t0
+    tk = torch.tensor(k, device=dev)
+    ty = torch.tensor(y, device=dev)
+    solves = {}
+    for gemm in ("native", "bf16x3"):
+        deblur.solve(tk, ty, L, 2, eta, gemm=gemm)  # warm-up
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        xs, losses = deblur.solve(tk, ty, L, steps, eta, gemm=gemm)
+        e1.record()
+        torch.cuda.synchronize()
+        solves["fp32" if gemm == "native" else gemm] = {
+            "ms_per_step": round(e0.elapsed_time(e1) / steps, 4),
+            "loss_first": losses[0], "loss_last": losses[-1],
+            "loss_rel_err_vs_oracle_max": max(abs(l1 - l2) / l2 for l1, l2 in zip(losses, loss_ref)),
+            "rel_err_X50_vs_oracle": rel(xs.cpu().numpy(), x_ref)}
+    out["deblur_256x256x128_L3_50_steps"] = {"solves": solves, "oracle_s": round(oracle_s, 2),
+                                             "eta": eta}
+    line = {
+        "metric": "workloads beside the step: FP64 small-case latency, w-svd PSNR, precision "
+                  "modes at 1024x1024x128, 50-step deblurring",
+        "n_gpus": 1,
+        "data": "synthetic",
+        "config": {"workload": "see keys"},
+        "results": out,
     }
     print(json.dumps(line), flush=True)
 
