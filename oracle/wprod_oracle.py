@@ -39,7 +39,8 @@ __all__ = [
     "check_levels", "lift_fwd", "lift_inv", "lift_fwd_adj", "lift_inv_adj",
     "face", "w_product", "w_product_vjp", "transpose", "identity", "inverse",
     "trace", "slice_svd", "w_svd", "w_svd_sparse", "spatial_factors", "w_pinv", "psnr",
-    "lsq_grad", "deblur_gd", "coefficient_weights",
+    "lsq_grad", "deblur_gd", "coefficient_weights", "w_pinv_sparse", "toeplitz_blur",
+    "pinv_deblur",
 ]
 
 
@@ -320,6 +321,52 @@ def w_pinv(a, L, rtol=None):
         inv = np.array([1.0 / x if x > cut else 0.0 for x in s])
         out[c] = (vt.T * inv) @ u.T
     return lift_inv(out, L)
+
+
+def w_pinv_sparse(a, L, rtol=None):
+    """Sparse Moore-Penrose inverse (the sp-w-product deblurring of Sec. IV-C).
+
+    As w_pinv, but only the coarsest coefficient blocks s_L and d_L (slices
+    [0, 2p/2^L)) are inverted; the finer detail slices of the result are zero.
+    Requires L >= 1.
+    """
+    ah = lift_fwd(a, L)
+    p, n1, n2 = ah.shape
+    if L < 1:
+        raise ValueError("the sparse pseudo-inverse needs L >= 1")
+    if rtol is None:
+        rtol = max(n1, n2) * np.finfo(np.float64).eps
+    out = np.zeros((p, n2, n1))
+    for c in range(2 * (p >> L)):
+        u, s, vt = np.linalg.svd(ah[c], full_matrices=False)
+        cut = rtol * (s[0] if s.size else 0.0)
+        inv = np.array([1.0 / x if x > cut else 0.0 for x in s])
+        out[c] = (vt.T * inv) @ u.T
+    return lift_inv(out, L)
+
+
+def toeplitz_blur(n, b):
+    """Linear blur matrix of Sec. IV-C: entry (i, j) = c(|i - j|) with
+    c(j) = (b - j) / (3 b) for 0 <= j < b and 0 otherwise."""
+    out = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            dist = abs(i - j)
+            if dist < b:
+                out[i, j] = (b - dist) / (3.0 * b)
+    return out
+
+
+def pinv_deblur(bt, av, ah, L, sparse=False):
+    """Least-squares deblurring of Sec. IV-C: X = A_V^+ *_w B *_w (A_H^T)^+.
+
+    bt: blurred tensor (p, n1, n2); av: (p, n1, n1); ah: (p, n2, n2).  With
+    sparse=True the pseudo-inverses are the sparse ones (sp-w-product).
+    (A_H^T)^+ = (A_H^+)^T, since the pseudo-inverse acts per coefficient slice
+    and the transpose commutes with W (Thm 2.1).
+    """
+    pinv = w_pinv_sparse if sparse else w_pinv
+    return w_product(w_product(pinv(av, L), bt, L), pinv(ah, L), L, trans_b=True)
 
 
 def coefficient_weights(p, L):

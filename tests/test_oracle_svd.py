@@ -196,3 +196,65 @@ def test_sparse_w_svd_error_identity():
 def test_sparse_w_svd_rejects_level_zero():
     with pytest.raises(ValueError):
         orc.w_svd_sparse(np.zeros((4, 3, 3)), 0, 1)
+
+
+# ---- pseudo-inverse deblurring (Sec. IV-C) -------------------------------------
+
+def test_toeplitz_blur_entries():
+    # b = 3: first row 1/3, 2/9, 1/9, 0, ... (c(j) = (b - j) / (3b)), symmetric.
+    t = orc.toeplitz_blur(5, 3)
+    np.testing.assert_allclose(t[0], [1 / 3, 2 / 9, 1 / 9, 0, 0], atol=1e-15)
+    np.testing.assert_allclose(t[2], [1 / 9, 2 / 9, 1 / 3, 2 / 9, 1 / 9], atol=1e-15)
+    np.testing.assert_array_equal(t, t.T)
+
+
+def test_sparse_pinv_is_pinv_without_fine_details():
+    # Identical frontal slices have no detail coefficients at all; the sparse and
+    # full pseudo-inverses then agree, and both equal the slice pinv repeated.
+    rng = np.random.default_rng(60)
+    m = rng.standard_normal((6, 4))
+    a = np.stack([m] * 8)
+    full = orc.w_pinv(a, 2)
+    sp = orc.w_pinv_sparse(a, 2)
+    np.testing.assert_allclose(sp, full, atol=1e-12)
+    np.testing.assert_allclose(full, np.stack([np.linalg.pinv(m)] * 8), atol=1e-12)
+
+
+def test_sparse_pinv_keeps_only_coarse_blocks():
+    rng = np.random.default_rng(61)
+    a = rng.standard_normal((16, 5, 5))
+    sp_hat = orc.lift_fwd(orc.w_pinv_sparse(a, 2), 2)
+    full_hat = orc.lift_fwd(orc.w_pinv(a, 2), 2)
+    np.testing.assert_allclose(sp_hat[:8], full_hat[:8], atol=1e-12)   # s_2 and d_2
+    assert np.abs(sp_hat[8:]).max() <= 1e-14 * np.abs(full_hat).max()  # d_1 dropped
+
+
+def test_pinv_deblur_recovers_the_coarse_part():
+    # With invertible slice blurs, A_V *_w X *_w A_H^T keeps only s_L of X (the
+    # blur tensors have no detail coefficients) and the deblurring returns
+    # exactly that coarse part: W^{-1}(Xhat_{s_L}, 0, ..., 0).
+    rng = np.random.default_rng(62)
+    p, n1, n2, L = 8, 7, 5, 2
+    av = np.stack([np.eye(n1) + 0.2 * rng.standard_normal((n1, n1))] * p)
+    ah = np.stack([np.eye(n2) + 0.2 * rng.standard_normal((n2, n2))] * p)
+    x = rng.standard_normal((p, n1, n2))
+    bt = orc.w_product(orc.w_product(av, x, L), ah, L, trans_b=True)
+    xh = orc.lift_fwd(x, L)
+    xh[p >> L:] = 0
+    coarse = orc.lift_inv(xh, L)
+    for sparse in (False, True):
+        np.testing.assert_allclose(orc.pinv_deblur(bt, av, ah, L, sparse), coarse, atol=1e-11)
+
+
+def test_pinv_deblur_is_least_squares():
+    # For general (slice-varying) operators the deblurred X satisfies the normal
+    # equations slice by slice in the wavelet domain: A^T (A X B^T - Y) B = 0.
+    rng = np.random.default_rng(63)
+    p, n1, n2, L = 4, 6, 4, 1
+    av = rng.standard_normal((p, n1 + 2, n1))     # tall: full column rank
+    ah = rng.standard_normal((p, n2 + 1, n2))
+    y = rng.standard_normal((p, n1 + 2, n2 + 1))
+    x = orc.w_product(orc.w_product(orc.w_pinv(av, L), y, L), orc.w_pinv(ah, L), L, trans_b=True)
+    r = orc.w_product(orc.w_product(av, x, L), ah, L, trans_b=True) - y
+    g = orc.w_product(orc.w_product(av, r, L, trans_a=True), ah, L)
+    assert np.abs(g).max() <= 1e-10 * np.abs(y).max()
