@@ -15,10 +15,12 @@ the kernels run on).  FP32 and plain BF16 forward+backward are timed beside it
 outside the timed steps.  Prints one JSON line.
 
 With --sp-w-svd it instead compares w-svd and sp-w-svd (Sec. IV-B) on a
-256x192x96 hyperspectral-like cube at L = 5 and prints that JSON line.
+256x192x96 hyperspectral-like cube at L = 5; --pinv-deblur times the
+pseudo-inverse deblurring of Sec. IV-C; --table1 the p x p x p w-products of
+Table 1; --configs the other workloads.  Each prints its own JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--sp-w-svd]
+                       [--sp-w-svd | --pinv-deblur | --table1 | --configs]
 """
 
 import argparse
@@ -57,6 +59,9 @@ def parse():
     ap.add_argument("--table1", action="store_true",
                     help="instead of the step: w-product of p x p x p tensors, p = 2 .. 1024 "
                          "(the shapes of the paper's Table 1), L = log2 p")
+    ap.add_argument("--pinv-deblur", action="store_true",
+                    help="instead of the step: pseudo-inverse deblurring (Sec. IV-C) of "
+                         "PaviaU- and Salinas-shaped hyperspectral-like cubes, FP64")
     ap.add_argument("--configs", action="store_true",
                     help="instead of the step: the other workloads (FP64 small case, config-3 "
                          "PSNR, 1024x1024x128 precision modes, 50-step deblurring solve)")
@@ -126,6 +131,9 @@ def main():
         return
     if args.table1:
         table1_report(torch, wp, dev, args)
+        return
+    if args.pinv_deblur:
+        deblur_report(torch, wp, synth, dev, args)
         return
 
     a = synth.normal_device((P, N1, N2), 21, dev)
@@ -362,6 +370,129 @@ def sparse_report(torch, wp, synth, dev, args):
                       "by rank)",
             "ms": cpu_ms},
     }
+    print(json.dumps(line), flush=True)
+
+
+# Sec. IV-C deblurring problems that fit the slice-SVD limit (n1, n2 <= 1024):
+# (name, n1, n2, p, L, the paper's w-product and sp-w-product times in s).
+DEBLUR_CASES = [("PaviaU", 610, 340, 102, 1, 9.8508, 9.7492),
+                ("Salinas", 512, 217, 204, 2, 10.9848, 6.5197)]
+DEBLUR_B = 10
+
+
+def deblur_report(torch, wp, synth, dev, args):
+    """Pseudo-inverse deblurring X = A_V^+ *_w B *_w (A_H^T)^+ (Sec. IV-C), FP64.
+
+    Per case: a hyperspectral-like cube X of the image's shape, the linear
+    blur (b = 10) stacked over the bands, B = A_V *_w X *_w A_H^T built on the
+    GPU outside the timed region; then the whole deblurring (two w_pinv, two
+    w_product calls) timed with HIP events, full and sparse (sp-w-product),
+    with a per-call breakdown.  Checked on sampled coarse coefficient slices
+    against a direct solve with the blur matrices.  The FP64 oracle of the
+    PaviaU sparse deblurring is timed on the host for context.
+    """
+    import oracle
+    from paper_2601_08228_amd import deblur
+    reps = max(args.steps, 1)
+
+    def ev_ms(fn):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            r = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, r
+
+    def rel(x_, ref):
+        return float(np.linalg.norm((x_ - ref).ravel()) / np.linalg.norm(ref.ravel()))
+
+    def psnr(x_, ref):
+        return float(10.0 * np.log10(np.max(ref) ** 2 / np.mean((x_ - ref) ** 2)))
+
+    cases = {}
+    cpu = None
+    for name, n1, n2, p, L, paper_w, paper_sp in DEBLUR_CASES:
+        tv = synth.toeplitz_blur(n1, DEBLUR_B)
+        th = synth.toeplitz_blur(n2, DEBLUR_B)
+        av = torch.from_numpy(synth.stack_slices(tv, p)).to(dev)
+        ah = torch.from_numpy(synth.stack_slices(th, p)).to(dev)
+        x_true = synth.hsi_like(n1, n2, p, seed=41)
+        xt = torch.from_numpy(x_true).to(dev)
+        bt = wp.w_product(wp.w_product(av, xt, L), ah, L, trans_b=True)
+        torch.cuda.synchronize()
+        row = {"n1": n1, "n2": n2, "p": p, "L": L}
+        for sparse in (False, True):
+            key = "sp_w_product" if sparse else "w_product"
+            ms, (x, (iv, ih)) = ev_ms(lambda: deblur.pinv_deblur(bt, av, ah, L, sparse=sparse))
+            # Breakdown of one call.
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            ev[0].record()
+            pv, _ = wp.w_pinv(av, L, sparse=sparse)
+            ev[1].record()
+            ph, _ = wp.w_pinv(ah, L, sparse=sparse)
+            ev[2].record()
+            t = wp.w_product(pv, bt, L)
+            ev[3].record()
+            wp.w_product(t, ph, L, trans_b=True)
+            ev[4].record()
+            torch.cuda.synchronize()
+            xs = x.cpu().numpy()
+            xhat = oracle.lift_fwd(xs, L)
+            bhat = oracle.lift_fwd(bt.cpu().numpy(), L)
+            errs = []
+            for c in (0, (p >> L) // 2, (p >> L) - 1):
+                want = np.linalg.solve(tv, np.linalg.solve(th, bhat[c].T).T)
+                errs.append(rel(xhat[c], want))
+            row[key] = {
+                "ms": round(ms, 3),
+                "pinv_av_ms": round(ev[0].elapsed_time(ev[1]), 3),
+                "pinv_ah_ms": round(ev[1].elapsed_time(ev[2]), 3),
+                "w_products_ms": round(ev[2].elapsed_time(ev[4]), 3),
+                "jacobi_sweeps_max": int(max(iv.max().item(), ih.max().item())),
+                "converged": bool(min(iv.min().item(), ih.min().item()) > 0),
+                "psnr_db": round(psnr(xs, x_true), 3),
+                "coarse_rel_err_vs_solve_max": max(errs),
+                "paper_s": paper_sp if sparse else paper_w,
+            }
+        row["psnr_blurred_db"] = round(psnr(bt.cpu().numpy(), x_true), 3)
+        cases[name] = row
+        if name == "PaviaU" and not args.no_cpu_baseline:
+            av_h, ah_h, bt_h = av.cpu().numpy(), ah.cpu().numpy(), bt.cpu().numpy()
+            t0 = time.perf_counter()
+            x_o = oracle.pinv_deblur(bt_h, av_h, ah_h, L, sparse=True)
+            cpu = {"ms": round((time.perf_counter() - t0) * 1e3, 1),
+                   "rel_err_gpu_vs_oracle": rel(x.cpu().numpy(), x_o)}
+        del av, ah, xt, bt
+        torch.cuda.empty_cache()
+    line = {
+        "metric": "pseudo-inverse deblurring time (FP64, sp-w-product, Salinas-shaped cube)",
+        "value": cases["Salinas"]["sp_w_product"]["ms"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": reps,
+        "warmup": args.warmup,
+        "higher_is_better": False,
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "pseudo-inverse deblurring X = A_V^+ *_w B *_w (A_H^T)^+ of "
+                               "hyperspectral-like cubes (12 components, noise 0.01) blurred by "
+                               "the linear Toeplitz blur b = 10 stacked over the bands; "
+                               "PaviaU 610x340x102 L=1 and Salinas 512x217x204 L=2 shapes; "
+                               "value: Salinas, sp-w-product",
+                   "blur_b": DEBLUR_B},
+        "cases": cases,
+    }
+    if cpu is not None:
+        line["cpu_baseline"] = {
+            "value": cpu["ms"], "unit": "ms", "cores": host_threads(), "kind": "oracle",
+            "sample": "FP64 NumPy oracle of the PaviaU sparse deblurring, whole cube, one call",
+            "rel_err_gpu_vs_oracle": cpu["rel_err_gpu_vs_oracle"]}
     print(json.dumps(line), flush=True)
 
 

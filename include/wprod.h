@@ -175,6 +175,26 @@ wp_status w_svd_sparse(const void* a, int64_t n1, int64_t n2, int64_t p, int L, 
 /* Workspace bytes for w_svd_sparse (0 on invalid arguments). */
 size_t w_svd_sparse_workspace(int64_t n1, int64_t n2, int64_t p, int L, int k, int dtype);
 
+/* ---- Moore-Penrose inverse (Def. 2.6, Thm 2.6; deblurring of Sec. IV-C) ------
+ * out = A^+ = W^{-1}( V_c Sigma_c^+ U_c^T ) over the coefficient slices c of
+ * W(A), A (p, n1, n2), out (p, n2, n1) (caller-allocated, device).  The
+ * slice SVDs are the full-rank w-svd of w_svd; Sigma^+ inverts the singular
+ * values above rtol * sigma_max of the slice and zeroes the rest.
+ * rtol in [0, 1); 0 selects max(n1, n2) * machine epsilon of the data type.
+ * sparse != 0 inverts only s_L and d_L (the first 2 p / 2^L coefficient
+ * slices; needs L >= 1) and leaves the finer detail coefficients of A^+ zero
+ * (the sp-w-product of Sec. IV-C).
+ * info (device int32, one per inverted slice): Jacobi sweeps used by the
+ *   slice, negative if it did not converge (see w_svd).
+ * n1, n2 <= 1024.  ws must hold w_pinv_workspace(...) bytes.
+ */
+wp_status w_pinv(const void* a, void* out, int64_t n1, int64_t n2, int64_t p, int L,
+                 int sparse, double rtol, int32_t* info, int dtype,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for w_pinv (0 on invalid arguments). */
+size_t w_pinv_workspace(int64_t n1, int64_t n2, int64_t p, int L, int sparse, int dtype);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,7 @@ from .wprod import (  # noqa: F401
     w_transform, w_itransform, w_transform_adj, w_itransform_adj, w_transform_split,
     w_itransform_adj_split, w_face_product, w_face_product_split, w_product,
     w_product_workspace, w_svd, w_svd_workspace, w_svd_sparse, w_svd_sparse_workspace,
-    SvdResult,
+    SvdResult, w_pinv, w_pinv_workspace,
 )
 from .autograd import WProduct, w_product_ad  # noqa: F401
 from . import deblur, synth  # noqa: F401

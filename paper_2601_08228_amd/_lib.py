@@ -48,6 +48,9 @@ SIGNATURES = {
     "w_svd_sparse": (_c_int, [_vp, _c_i64, _c_i64, _c_i64, _c_int, _c_int, _vp, _vp, _vp, _vp,
                               _c_int, _vp, _vp, _c_int, _vp, _sz, _vp]),
     "w_svd_sparse_workspace": (_sz, [_c_i64, _c_i64, _c_i64, _c_int, _c_int, _c_int]),
+    "w_pinv": (_c_int, [_vp, _vp, _c_i64, _c_i64, _c_i64, _c_int, _c_int, ctypes.c_double, _vp,
+                        _c_int, _vp, _sz, _vp]),
+    "w_pinv_workspace": (_sz, [_c_i64, _c_i64, _c_i64, _c_int, _c_int, _c_int]),
 }
 
 _lib = None

@@ -360,4 +360,37 @@ wp_status w_svd_sparse(const void* a, int64_t n1, int64_t n2, int64_t p, int L, 
                        orth_err, dtype, ws, ws_bytes, stream);
 }
 
+size_t w_pinv_workspace(int64_t n1, int64_t n2, int64_t p, int L, int sparse, int dtype) {
+  int64_t elems = 0, nsl = 0;
+  const int k = int(n1 < n2 ? n1 : n2);
+  if (check_svd(n1, n2, p, L, k < 1 ? 1 : k, sparse != 0, dtype, &elems, &nsl) != WP_OK) return 0;
+  return wp::pinv_workspace_bytes(n1, n2, p, L, sparse != 0, dtype);
+}
+
+wp_status w_pinv(const void* a, void* out, int64_t n1, int64_t n2, int64_t p, int L, int sparse,
+                 double rtol, int32_t* info, int dtype, void* ws, size_t ws_bytes, void* stream) {
+  int64_t elems = 0, nsl = 0;
+  const int k = int(n1 < n2 ? n1 : n2);
+  const wp_status st = check_svd(n1, n2, p, L, k < 1 ? 1 : k, sparse != 0, dtype, &elems, &nsl);
+  if (st != WP_OK) return st;
+  if (!(rtol >= 0.0) || rtol >= 1.0) return WP_EINVAL;  // also rejects NaN
+  if (a == nullptr || out == nullptr || info == nullptr || ws == nullptr) return WP_ENULL;
+  const size_t need = wp::pinv_workspace_bytes(n1, n2, p, L, sparse != 0, dtype);
+  if (ws_bytes < need) return WP_EWORKSPACE;
+  const size_t es = dtype_size(dtype);
+  const Range ra = range_of(a, elems, es);
+  const Range outs[] = {range_of(out, elems, es), range_of(info, nsl, 4),
+                        Range{static_cast<const char*>(ws), static_cast<const char*>(ws) + ws_bytes}};
+  constexpr int nout = sizeof(outs) / sizeof(outs[0]);
+  for (int i = 0; i < nout; ++i) {
+    if (overlap(outs[i], ra)) return WP_EALIAS;
+    for (int j = i + 1; j < nout; ++j)
+      if (overlap(outs[i], outs[j])) return WP_EALIAS;
+  }
+  if (rtol == 0.0) rtol = double(n1 > n2 ? n1 : n2) * (dtype == WP_F64 ? 2.220446049250313e-16
+                                                                       : 1.1920928955078125e-07);
+  return from_hip(wp::launch_pinv(a, out, n1, n2, p, L, sparse != 0, rtol, info, dtype, ws,
+                                  static_cast<hipStream_t>(stream)));
+}
+
 }  // extern "C"

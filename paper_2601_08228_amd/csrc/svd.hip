@@ -878,7 +878,7 @@ __global__ __launch_bounds__(256) void zero_kernel(T* __restrict__ x, int64_t n)
 template <typename T>
 hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, bool sparse,
                    T* uhat, T* shat, T* vhat, T* ak, int max_sweeps, int32_t* info,
-                   double* orth_err, void* ws, hipStream_t s) {
+                   double* orth_err, void* ws, hipStream_t s, bool polish = true) {
   // sp-w-svd decomposes only s_L and d_L, the leading 2 p / 2^L coefficient
   // slices; the finer details are dropped (zero) in the rebuild.
   const int64_t nsl = sparse ? 2 * (p >> L) : p;
@@ -980,7 +980,7 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
     if (e != hipSuccess) return e;
   }
 
-  if (reg_ok && k <= 64) {
+  if (polish && reg_ok && k <= 64) {
     // Orthonormalise the recovered factor (after the rebuild, which uses the
     // recovered columns as they are: their product with U is the exact rank-k
     // projection U U^T A).
@@ -1002,7 +1002,110 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
   return e;
 }
 
+// Pseudo-inverse of sigma applied to the columns of vhat (n2 x k per slice):
+// column i is scaled by 1 / sigma_i when sigma_i > rtol * sigma_max, else
+// zeroed (Def. 2.6 per coefficient slice; sigma is sorted, sigma_max first).
+template <typename T>
+__global__ __launch_bounds__(256) void pinv_scale_kernel(T* __restrict__ v,
+                                                         const T* __restrict__ sh, int n2, int k,
+                                                         double rtol) {
+  const int64_t slice = blockIdx.y;
+  const T* sg = sh + slice * k;
+  const double cut = rtol * double(sg[0]);
+  T* vs = v + slice * n2 * k;
+  for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < int64_t(n2) * k;
+       e += int64_t(gridDim.x) * 256) {
+    const double si = double(sg[e % k]);
+    vs[e] = si > cut ? T(double(vs[e]) / si) : T(0);
+  }
+}
+
+struct PinvPlan {
+  size_t svd, uh, sh, vh, ph, total;
+};
+
+inline PinvPlan plan_pinv(int64_t n1, int64_t n2, int64_t p, int64_t nsl, size_t es) {
+  const int64_t k = n1 < n2 ? n1 : n2;
+  PinvPlan pl{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes, 256);
+    return at;
+  };
+  const SvdPlan sp = plan_svd(n1, n2, p, nsl, int(k), es);
+  pl.svd = take(sp.total);
+  pl.uh = take(size_t(nsl * n1 * k) * es);
+  pl.sh = take(size_t(nsl * k) * es);
+  pl.vh = take(size_t(nsl * n2 * k) * es);
+  pl.ph = take(size_t(p * n2 * n1) * es);
+  pl.total = off + 256;
+  return pl;
+}
+
+// A^+ = W^{-1}( Vhat_c Sigma_c^+ Uhat_c^T ) over the coefficient slices c (all
+// p, or only s_L and d_L when sparse; the rest of the coefficients are zero).
+// The recovered factor is used as recovered (no polish): with U from the
+// Jacobi columns and V = A^T U / sigma, V Sigma^+ U^T = A^T U Sigma^-2 U^T over
+// the kept values, which is A^+ for any U that spans the kept space.  A polish
+// step would mix the arbitrary columns of values under the cut (rank-deficient
+// slices) into the kept ones.
+template <typename T>
+hipError_t run_pinv(const T* a, T* out, int64_t n1, int64_t n2, int64_t p, int L, bool sparse,
+                    double rtol, int32_t* info, void* ws, hipStream_t s) {
+  const int64_t k = n1 < n2 ? n1 : n2;
+  const int64_t nsl = sparse ? 2 * (p >> L) : p;
+  const PinvPlan pl = plan_pinv(n1, n2, p, nsl, sizeof(T));
+  char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
+  T* uh = reinterpret_cast<T*>(base + pl.uh);
+  T* sh = reinterpret_cast<T*>(base + pl.sh);
+  T* vh = reinterpret_cast<T*>(base + pl.vh);
+  T* ph = reinterpret_cast<T*>(base + pl.ph);
+  hipError_t e = run_svd<T>(a, n1, n2, p, L, int(k), sparse, uh, sh, vh, static_cast<T*>(nullptr),
+                            0, info, nullptr, base + pl.svd, s, /*polish=*/false);
+  if (e != hipSuccess) return e;
+  const int64_t per = n2 * k;
+  const int64_t want = (per + 255) / 256;
+  hipLaunchKernelGGL((pinv_scale_kernel<T>), dim3(unsigned(want < 64 ? want : 64), unsigned(nsl)),
+                     dim3(256), 0, s, vh, sh, int(n2), int(k), rtol);
+  if (nsl < p) {
+    const int64_t tail = (p - nsl) * n2 * n1;
+    const int64_t wt = (tail + 255) / 256;
+    hipLaunchKernelGGL((zero_kernel<T>), dim3(unsigned(wt < 8192 ? wt : 8192)), dim3(256), 0, s,
+                       ph + nsl * n2 * n1, tail);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if constexpr (sizeof(T) == 8) {
+    e = launch_face_f64(reinterpret_cast<const double*>(vh), reinterpret_cast<const double*>(uh),
+                        reinterpret_cast<double*>(ph), n2, k, n1, nsl, false, true, s);
+    if (e == hipSuccess)
+      e = launch_lift_f64(LiftKind::kInverse, reinterpret_cast<const double*>(ph),
+                          reinterpret_cast<double*>(out), n2 * n1, p, L, s);
+  } else {
+    e = launch_face_f32(reinterpret_cast<const float*>(vh), reinterpret_cast<const float*>(uh),
+                        reinterpret_cast<float*>(ph), n2, k, n1, nsl, false, true, s);
+    if (e == hipSuccess)
+      e = launch_lift_f32(LiftKind::kInverse, reinterpret_cast<const float*>(ph),
+                          reinterpret_cast<float*>(out), n2 * n1, p, L, s);
+  }
+  return e;
+}
+
 }  // namespace
+
+size_t pinv_workspace_bytes(int64_t n1, int64_t n2, int64_t p, int L, bool sparse, int dtype) {
+  return plan_pinv(n1, n2, p, sparse ? 2 * (p >> L) : p, dtype == 0 ? 8 : 4).total;
+}
+
+hipError_t launch_pinv(const void* a, void* out, int64_t n1, int64_t n2, int64_t p, int L,
+                       bool sparse, double rtol, int32_t* info, int dtype, void* ws, hipStream_t s) {
+  if (dtype == 0)
+    return run_pinv<double>(static_cast<const double*>(a), static_cast<double*>(out), n1, n2, p, L,
+                            sparse, rtol, info, ws, s);
+  return run_pinv<float>(static_cast<const float*>(a), static_cast<float*>(out), n1, n2, p, L,
+                         sparse, rtol, info, ws, s);
+}
 
 size_t svd_workspace_bytes(int64_t n1, int64_t n2, int64_t p, int L, int k, bool sparse,
                            int dtype) {

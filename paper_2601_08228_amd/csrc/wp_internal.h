@@ -50,6 +50,11 @@ hipError_t launch_svd(const void* a, int64_t n1, int64_t n2, int64_t p, int L, i
                       bool sparse, void* uhat, void* shat, void* vhat, void* ak, int max_sweeps,
                       int32_t* info, double* orth_err, int dtype, void* ws, hipStream_t s);
 
+// Moore-Penrose inverse (Def. 2.6) through the same SVD; out is (p, n2, n1).
+size_t pinv_workspace_bytes(int64_t n1, int64_t n2, int64_t p, int L, bool sparse, int dtype);
+hipError_t launch_pinv(const void* a, void* out, int64_t n1, int64_t n2, int64_t p, int L,
+                       bool sparse, double rtol, int32_t* info, int dtype, void* ws, hipStream_t s);
+
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 }  // namespace wp

@@ -9,8 +9,9 @@ loss and the update are elementwise tensor operations on the device.
 import torch
 
 from .autograd import WProduct
+from . import wprod as _w
 
-__all__ = ["lsq_gradient", "solve"]
+__all__ = ["lsq_gradient", "solve", "pinv_deblur"]
 
 
 def lsq_gradient(k, x, y, L, gemm="native"):
@@ -38,3 +39,17 @@ def solve(k, y, L, steps, eta, gemm="native", x0=None):
         with torch.no_grad():
             x = (xv - eta * xv.grad).detach()
     return x, [float(v) for v in torch.stack(losses).cpu()]
+
+
+def pinv_deblur(b, av, ah, L, sparse=False, gemm="native"):
+    """X = A_V^+ *_w B *_w (A_H^T)^+ (Sec. IV-C) with library calls only:
+    two pseudo-inverses (sparse=True: sp-w-product) and two w-products, the
+    second with A_H^+ transposed ((A_H^T)^+ = (A_H^+)^T).
+
+    Returns (X, (info_v, info_h)); the info tensors report Jacobi convergence.
+    """
+    pv, info_v = _w.w_pinv(av, L, sparse=sparse)
+    ph, info_h = _w.w_pinv(ah, L, sparse=sparse)
+    t = _w.w_product(pv, b, L, gemm=gemm)
+    x = _w.w_product(t, ph, L, trans_b=True, gemm=gemm)
+    return x, (info_v, info_h)

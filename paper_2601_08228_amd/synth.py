@@ -13,7 +13,8 @@ spatially correlated abundance maps, values in [0, 1], few components.
 
 import numpy as np
 
-__all__ = ["normal", "uniform", "hsi_like", "gaussian_band", "stack_slices", "normal_device",
+__all__ = ["normal", "uniform", "hsi_like", "gaussian_band", "toeplitz_blur", "stack_slices",
+           "normal_device",
            "uniform_device"]
 
 
@@ -86,6 +87,13 @@ def gaussian_band(n, sigma=1.5, half_width=4):
         for j in range(max(0, i - half_width), min(n, i + half_width + 1)):
             g[i, j] = np.exp(-((i - j) ** 2) / (2.0 * sigma ** 2)) / z
     return g
+
+
+def toeplitz_blur(n, b):
+    """Linear-decay blur matrix of the deblurring experiment (Sec. IV-C), n x n:
+    T[i, j] = (b - |i - j|) / (3 b) for |i - j| < b, zero elsewhere."""
+    dist = np.abs(np.arange(n)[:, None] - np.arange(n)[None, :]).astype(np.float64)
+    return np.where(dist < b, (b - dist) / (3.0 * b), 0.0)
 
 
 def stack_slices(mat, p):

@@ -19,7 +19,8 @@ __all__ = [
     "w_transform", "w_itransform", "w_transform_adj", "w_itransform_adj",
     "w_transform_split", "w_itransform_adj_split", "w_face_product",
     "w_face_product_split", "w_product", "w_product_workspace", "w_svd",
-    "w_svd_workspace", "w_svd_sparse", "w_svd_sparse_workspace", "SvdResult",
+    "w_svd_workspace", "w_svd_sparse", "w_svd_sparse_workspace", "SvdResult", "w_pinv",
+    "w_pinv_workspace",
 ]
 
 _DT = {torch.float64: _lib.WP_F64, torch.float32: _lib.WP_F32}
@@ -241,3 +242,32 @@ def w_svd_sparse(a, L, k, max_sweeps=0, want_ak=True, want_orth=True, workspace=
     p = a.shape[0] if a.dim() == 3 else 0
     nsl = 2 * (p >> int(L)) if int(L) >= 1 else 0
     return _svd_call("w_svd_sparse", a, L, k, nsl, max_sweeps, want_ak, want_orth, workspace)
+
+
+def w_pinv_workspace(n1, n2, p, L, sparse=False, dtype=torch.float64):
+    return int(_lib.load().w_pinv_workspace(n1, n2, p, int(L), int(bool(sparse)), _DT[dtype]))
+
+
+def w_pinv(a, L, sparse=False, rtol=0.0, workspace=None):
+    """Moore-Penrose inverse A^+ (Def. 2.6): returns (out (p, n2, n1), info).
+
+    sparse=True inverts only s_L and d_L (sp-w-product, Sec. IV-C).  rtol = 0
+    selects max(n1, n2) * machine epsilon.  info (int32 device tensor, one per
+    inverted coefficient slice) is negative for a slice whose SVD did not
+    converge.  Nothing is synchronised.
+    """
+    _dev_tensor(a, "a", tuple(_DT))
+    p, n1, n2 = a.shape
+    nsl = (2 * (p >> int(L)) if int(L) >= 1 else 0) if sparse else p
+    out = torch.empty((p, n2, n1), dtype=a.dtype, device=a.device)
+    info = torch.empty((max(nsl, 0),), dtype=torch.int32, device=a.device)
+    lib = _lib.load()
+    need = lib.w_pinv_workspace(n1, n2, p, int(L), int(bool(sparse)), _DT[a.dtype])
+    if workspace is None:
+        workspace = torch.empty(max(int(need), 1), dtype=torch.uint8, device=a.device)
+    with torch.cuda.device(a.device):
+        st = lib.w_pinv(_ptr(a), _ptr(out), n1, n2, p, int(L), int(bool(sparse)), float(rtol),
+                        _ptr(info), _DT[a.dtype], _ptr(workspace),
+                        workspace.numel() * workspace.element_size(), _stream(a))
+    _lib.check("w_pinv", st)
+    return out, info

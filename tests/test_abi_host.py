@@ -31,8 +31,8 @@ def test_header_declares_expected_entry_points():
     for must in ["w_transform", "w_itransform", "w_transform_adj", "w_itransform_adj",
                  "w_transform_split", "w_itransform_adj_split", "w_face_product",
                  "w_face_product_split", "w_product", "w_product_workspace", "w_svd",
-                 "w_svd_workspace", "w_svd_sparse", "w_svd_sparse_workspace",
-                 "w_status_string", "w_version"]:
+                 "w_svd_workspace", "w_svd_sparse", "w_svd_sparse_workspace", "w_pinv",
+                 "w_pinv_workspace", "w_status_string", "w_version"]:
         assert must in names, must
 
 
@@ -158,6 +158,33 @@ def test_sparse_svd_validation(lib):
     # uhat holds 8 slices * 8 * 3 floats = 768 bytes; shat inside it is an alias.
     assert f(A, 8, 6, 16, 2, 3, U, ctypes.c_void_p(0x500000 + 764), V, AK, 0, INFO, ORTH, 1, W,
              need, NULL) == -3
+
+
+def test_pinv_validation(lib):
+    need = lib.w_pinv_workspace(8, 6, 16, 2, 0, 1)
+    assert need > 0
+    assert 0 < lib.w_pinv_workspace(8, 6, 16, 2, 1, 1) < need     # sparse: 8 of 16 slices
+    assert lib.w_pinv_workspace(8, 6, 16, 0, 1, 1) == 0            # sparse needs L >= 1
+    assert lib.w_pinv_workspace(8, 6, 12, 3, 0, 1) == 0            # p not divisible by 2^L
+    assert lib.w_pinv_workspace(1100, 6, 16, 2, 0, 1) == 0         # n1 > 1024
+    assert lib.w_pinv_workspace(8, 6, 16, 2, 0, 2) == 0            # bad dtype code
+    f = lib.w_pinv
+    OUT, INFO = ctypes.c_void_p(0x500000), ctypes.c_void_p(0x900000)
+    W = ctypes.c_void_p(0x10000000)
+    assert f(A, OUT, 8, 6, 12, 3, 0, 0.0, INFO, 1, W, need, NULL) == -1
+    assert f(A, OUT, 8, 6, 16, 2, 0, -1e-3, INFO, 1, W, need, NULL) == -1
+    assert f(A, OUT, 8, 6, 16, 2, 0, float("nan"), INFO, 1, W, need, NULL) == -1
+    assert f(A, OUT, 8, 6, 16, 2, 0, 1.0, INFO, 1, W, need, NULL) == -1
+    assert f(A, OUT, 8, 6, 16, 2, 0, 0.0, INFO, 2, W, need, NULL) == -4
+    assert f(A, NULL, 8, 6, 16, 2, 0, 0.0, INFO, 1, W, need, NULL) == -2
+    assert f(A, OUT, 8, 6, 16, 2, 0, 0.0, NULL, 1, W, need, NULL) == -2
+    assert f(A, OUT, 8, 6, 16, 2, 0, 0.0, INFO, 1, W, need - 1, NULL) == -5
+    # a holds 16 * 8 * 6 floats = 3072 bytes: an output starting inside it aliases.
+    assert f(A, ctypes.c_void_p(0x100000 + 3068), 8, 6, 16, 2, 0, 0.0, INFO, 1, W, need,
+             NULL) == -3
+    # info (16 int32) overlapping the output.
+    assert f(A, OUT, 8, 6, 16, 2, 0, 0.0, ctypes.c_void_p(0x500000 + 3068), 1, W, need,
+             NULL) == -3
 
 
 def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):

@@ -208,6 +208,13 @@ def test_toeplitz_blur_entries():
     np.testing.assert_array_equal(t, t.T)
 
 
+def test_input_generator_blur_matches_the_oracle():
+    # The seeded input module builds the same blur as the oracle's definition.
+    from paper_2601_08228_amd import synth
+    for n, b in ((5, 3), (40, 10), (17, 1)):
+        np.testing.assert_array_equal(synth.toeplitz_blur(n, b), orc.toeplitz_blur(n, b))
+
+
 def test_sparse_pinv_is_pinv_without_fine_details():
     # Identical frontal slices have no detail coefficients at all; the sparse and
     # full pseudo-inverses then agree, and both equal the slice pinv repeated.
