@@ -61,7 +61,7 @@ def parse():
                          "(the shapes of the paper's Table 1), L = log2 p")
     ap.add_argument("--pinv-deblur", action="store_true",
                     help="instead of the step: pseudo-inverse deblurring (Sec. IV-C) of "
-                         "PaviaU- and Salinas-shaped hyperspectral-like cubes, FP64")
+                         "PaviaU-, Salinas- and Botswana-shaped hyperspectral-like cubes, FP64")
     ap.add_argument("--configs", action="store_true",
                     help="instead of the step: the other workloads (FP64 small case, config-3 "
                          "PSNR, 1024x1024x128 precision modes, 50-step deblurring solve)")
@@ -373,10 +373,11 @@ def sparse_report(torch, wp, synth, dev, args):
     print(json.dumps(line), flush=True)
 
 
-# Sec. IV-C deblurring problems that fit the slice-SVD limit (n1, n2 <= 1024):
+# Sec. IV-C deblurring problems, Table 4 shapes and levels:
 # (name, n1, n2, p, L, the paper's w-product and sp-w-product times in s).
 DEBLUR_CASES = [("PaviaU", 610, 340, 102, 1, 9.8508, 9.7492),
-                ("Salinas", 512, 217, 204, 2, 10.9848, 6.5197)]
+                ("Salinas", 512, 217, 204, 2, 10.9848, 6.5197),
+                ("Botswana", 1476, 256, 144, 4, 40.5728, 7.3428)]
 DEBLUR_B = 10
 
 
@@ -483,7 +484,8 @@ def deblur_report(torch, wp, synth, dev, args):
         "config": {"workload": "pseudo-inverse deblurring X = A_V^+ *_w B *_w (A_H^T)^+ of "
                                "hyperspectral-like cubes (12 components, noise 0.01) blurred by "
                                "the linear Toeplitz blur b = 10 stacked over the bands; "
-                               "PaviaU 610x340x102 L=1 and Salinas 512x217x204 L=2 shapes; "
+                               "PaviaU 610x340x102 L=1, Salinas 512x217x204 L=2 and "
+                               "Botswana 1476x256x144 L=4 shapes; "
                                "value: Salinas, sp-w-product",
                    "blur_b": DEBLUR_B},
         "cases": cases,

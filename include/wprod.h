@@ -148,7 +148,7 @@ size_t w_product_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int L,
  * orth_err (2 doubles, device, or NULL): max over slices of
  *   max|uhat^T uhat - I| and of max|vhat^T vhat - I|, evaluated in FP64.
  * 1 <= k <= min(n1, n2); max_sweeps >= 1 (<= 0 selects 30 for F64, 20 for F32);
- * n1, n2 <= 1024.  ws must hold w_svd_workspace(...) bytes.
+ * n1, n2 <= 2048.  ws must hold w_svd_workspace(...) bytes.
  */
 wp_status w_svd(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k,
                 void* uhat, void* shat, void* vhat, void* ak, int max_sweeps,
@@ -186,7 +186,7 @@ size_t w_svd_sparse_workspace(int64_t n1, int64_t n2, int64_t p, int L, int k, i
  * (the sp-w-product of Sec. IV-C).
  * info (device int32, one per inverted slice): Jacobi sweeps used by the
  *   slice, negative if it did not converge (see w_svd).
- * n1, n2 <= 1024.  ws must hold w_pinv_workspace(...) bytes.
+ * n1, n2 <= 2048.  ws must hold w_pinv_workspace(...) bytes.
  */
 wp_status w_pinv(const void* a, void* out, int64_t n1, int64_t n2, int64_t p, int L,
                  int sparse, double rtol, int32_t* info, int dtype,

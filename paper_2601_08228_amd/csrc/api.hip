@@ -298,7 +298,7 @@ wp_status check_svd(int64_t n1, int64_t n2, int64_t p, int L, int k, bool sparse
   const wp_status st = check_tensor(n1, n2, p, L, elems);
   if (st != WP_OK) return st;
   if (sparse && L < 1) return WP_EINVAL;
-  if (k < 1 || k > n1 || k > n2 || n1 > 1024 || n2 > 1024) return WP_EINVAL;
+  if (k < 1 || k > n1 || k > n2 || n1 > 2048 || n2 > 2048) return WP_EINVAL;
   *nsl = sparse ? 2 * (p >> L) : p;
   return WP_OK;
 }

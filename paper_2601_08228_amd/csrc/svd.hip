@@ -41,7 +41,8 @@ namespace {
 
 constexpr int kJacobiWaves = 8;
 constexpr int kJacobiThreads = 64 * kJacobiWaves;
-constexpr int kPairBatch = 4;
+// Largest slice side handled (rows and columns of W).
+constexpr int kMaxSide = 2048;
 
 template <typename T>
 struct Unit;
@@ -118,16 +119,15 @@ __device__ __forceinline__ int rotation(double al, double be, double ga, double 
   return 1;
 }
 
-// Singular values, ranking and the k leading factors from the converged W and
-// V (column c of W at W + c*mr, of V at V + c*nc).  Called by every thread of
-// the workgroup.  With V == nullptr only the factor taken from W is written
-// (U when n1 >= n2, vhat otherwise; U * sigma too in the first case); the
-// other one is recovered afterwards from the coefficients (recover_kernel).
+// Singular values, ranking and the k leading columns of the factor formed by
+// W (column c at W + c * mr), called by every thread of the workgroup: U (and
+// U * sigma) when n1 >= n2, vhat otherwise.  The other factor is recovered
+// afterwards from the coefficients (recover_kernel), which in the second case
+// also fixes the signs.
 template <typename T>
-__device__ void emit_factors(const T* __restrict__ W, const T* __restrict__ V, const SvdDims& d,
-                             int slice, T* __restrict__ uhat, T* __restrict__ shat,
-                             T* __restrict__ vhat, T* __restrict__ us, double* s_sigma,
-                             int* s_order) {
+__device__ void emit_factors(const T* __restrict__ W, const SvdDims& d, int slice,
+                             T* __restrict__ uhat, T* __restrict__ shat, T* __restrict__ vhat,
+                             T* __restrict__ us, double* s_sigma, int* s_order) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int mr = d.mr, nc = d.nc;
@@ -158,8 +158,6 @@ __device__ void emit_factors(const T* __restrict__ W, const T* __restrict__ V, c
   }
   __syncthreads();
 
-  // U column i has n1 entries, V column i has n2 entries.  Without transposition
-  // U = W_c / sigma (mr = n1 rows) and V = V_c (nc = n2 rows); with it the roles swap.
   const int k = d.k;
   T* U = uhat + int64_t(slice) * d.n1 * k;
   T* Vo = vhat + int64_t(slice) * d.n2 * k;
@@ -168,26 +166,19 @@ __device__ void emit_factors(const T* __restrict__ W, const T* __restrict__ V, c
     const int c = s_order[i];
     const double sg = s_sigma[c];
     const double inv = sg > 0 ? 1.0 / sg : 0.0;
-    if (V == nullptr && d.trans) {
-      // W holds the transposed slice: W_c / sigma is a right singular vector;
-      // its sign follows the recovered U column.
-      for (int row = lane; row < d.n2; row += 64)
-        Vo[int64_t(row) * k + i] = T(double(W[int64_t(c) * mr + row]) * inv);
-      if (lane == 0) shat[int64_t(slice) * k + i] = T(sg);
+    const T* w = W + int64_t(c) * mr;
+    if (lane == 0) shat[int64_t(slice) * k + i] = T(sg);
+    if (d.trans) {
+      // W holds the transposed slice: w_c / sigma is a right singular vector.
+      for (int row = lane; row < mr; row += 64) Vo[int64_t(row) * k + i] = T(double(w[row]) * inv);
       continue;
     }
-    auto ucol = [&](int row) -> double {
-      return d.trans ? double(V[int64_t(c) * nc + row]) : double(W[int64_t(c) * mr + row]) * inv;
-    };
-    auto vcol = [&](int row) -> double {
-      return d.trans ? double(W[int64_t(c) * mr + row]) * inv : double(V[int64_t(c) * nc + row]);
-    };
-    // Largest |U| entry, lowest row on ties.
+    // Largest |U| entry, lowest row on ties, made positive.
     double best = -1.0;
     int brow = 0x7fffffff;
     double bval = 0;
-    for (int row = lane; row < d.n1; row += 64) {
-      const double x = ucol(row);
+    for (int row = lane; row < mr; row += 64) {
+      const double x = double(w[row]) * inv;
       const double ax = fabs(x);
       if (ax > best) {
         best = ax;
@@ -207,136 +198,254 @@ __device__ void emit_factors(const T* __restrict__ W, const T* __restrict__ V, c
       }
     }
     const double sgn = bval < 0 ? -1.0 : 1.0;
-    for (int row = lane; row < d.n1; row += 64) {
-      const double x = sgn * ucol(row);
+    for (int row = lane; row < mr; row += 64) {
+      const double x = sgn * double(w[row]) * inv;
       U[int64_t(row) * k + i] = T(x);
       Us[int64_t(row) * k + i] = T(T(x) * T(sg));
     }
-    if (V != nullptr)
-      for (int row = lane; row < d.n2; row += 64) Vo[int64_t(row) * k + i] = T(sgn * vcol(row));
-    if (lane == 0) shat[int64_t(slice) * k + i] = T(sg);
   }
 }
 
-// General kernel: W and V in the workspace.  RPL: rows per lane (mr <= 64 * RPL).
-template <typename T, int RPL>
-__global__ __launch_bounds__(kJacobiThreads) void jacobi_global_kernel(
-    const T* __restrict__ ah, T* __restrict__ wbuf, T* __restrict__ vbuf, SvdDims d,
-    int max_sweeps, T* __restrict__ uhat, T* __restrict__ shat, T* __restrict__ vhat,
-    T* __restrict__ us, int32_t* __restrict__ info) {
-  const int slice = blockIdx.x;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int mr = d.mr, nc = d.nc, ncp = d.ncp;
+// ---- Block one-sided Jacobi (slices beyond the register-resident kernel) ----
+// W (mr x nc, column c at W + c * mr) is padded with zero columns to
+// nbp * B columns, grouped in nbp blocks of B.  A sweep is a round-robin
+// tournament over the blocks: nbp - 1 rounds of nbp / 2 block pairs, one
+// launch per round and one workgroup per (block pair, slice), so a slice is
+// spread over many compute units.  The workgroup holds its two blocks in
+// registers: B groups of GL = 512 / B lanes, group g keeps column g of the
+// first block and, in sub-round t, column (g + t) mod B of the second, which
+// advances one group per sub-round through LDS; all B * B cross pairs are
+// rotated.  In the first round of a sweep each block also rotates its own
+// B (B - 1) / 2 pairs (round-robin over the block, columns in LDS), so every
+// column pair of the slice is visited exactly once per sweep, with the same
+// rotation and threshold as the one-workgroup kernel.  Per-slice control words
+// count the rotations of a sweep; a slice stops (its later launches return at
+// once) after a sweep without rotation, on a non-finite value, or after the
+// sweep limit.  Only W is kept; the second factor is recovered afterwards.
+
+constexpr int kBjThreads = 512;
+
+struct BjCtl {
+  int state;   // 0 running, 1 converged, 2 non-finite value, 3 out of sweeps
+  int sweeps;  // sweeps completed
+  int rot;     // rotations in the current sweep
+  int bad;     // non-finite value seen in the current sweep
+};
+
+// Block width and rows per lane of the block kernel for mr rows.
+struct BjShape {
+  int B, rpl, nbp;
+};
+inline BjShape bj_shape(int mr, int nc) {
+  BjShape s{};
+  s.B = mr <= 1024 ? 16 : 8;
+  const int gl = kBjThreads / s.B;
+  s.rpl = ((mr + gl - 1) / gl + 3) / 4 * 4;
+  const int nb = (nc + s.B - 1) / s.B;
+  s.nbp = nb + (nb & 1);
+  return s;
+}
+
+template <int GL>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = GL / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+template <int GL>
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+  for (int o = GL / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Copies the slices into column-major W through 32 x 32 LDS tiles (coalesced
+// on both sides for either orientation) and zeroes the padding columns.
+template <typename T>
+__global__ __launch_bounds__(256) void bj_init_kernel(const T* __restrict__ ah,
+                                                      T* __restrict__ wbuf, SvdDims d, int ncb) {
+  __shared__ T tile[32][33];
+  const int slice = blockIdx.z;
+  const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
   const T* a = ah + int64_t(slice) * d.n1 * d.n2;
-  T* W = wbuf + int64_t(slice) * nc * mr;   // column c at W + c*mr
-  T* V = vbuf + int64_t(slice) * nc * nc;   // column c at V + c*nc
-
-  __shared__ int s_rot;
-  __shared__ int s_bad;
-  __shared__ double s_sigma[1024];
-  __shared__ int s_order[1024];
-
-  // ---- copy the slice into column-major W, V = I ---------------------------
-  for (int64_t e = threadIdx.x; e < int64_t(mr) * nc; e += kJacobiThreads) {
-    const int c = int(e / mr), r = int(e % mr);
-    // W[r][c]: slice entry (r, c) if not transposed, (c, r) otherwise.
-    W[e] = d.trans ? a[int64_t(c) * d.n2 + r] : a[int64_t(r) * d.n2 + c];
+  T* W = wbuf + int64_t(slice) * ncb * d.mr;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  // W[r][c] = slice (r, c) when not transposed (read along c), (c, r) otherwise
+  // (read along r); tile[r - r0][c - c0].
+  for (int y = ty; y < 32; y += 8) {
+    if (d.trans) {
+      const int r = r0 + tx, c = c0 + y;
+      tile[tx][y] = (r < d.mr && c < d.nc) ? a[int64_t(c) * d.n2 + r] : T(0);
+    } else {
+      const int r = r0 + y, c = c0 + tx;
+      tile[y][tx] = (r < d.mr && c < d.nc) ? a[int64_t(r) * d.n2 + c] : T(0);
+    }
   }
-  for (int64_t e = threadIdx.x; e < int64_t(nc) * nc; e += kJacobiThreads) {
-    const int c = int(e / nc), r = int(e % nc);
-    V[e] = T(r == c ? 1 : 0);
-  }
-  if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int r = r0 + tx, c = c0 + y;
+    if (r < d.mr && c < ncb) W[int64_t(c) * d.mr + r] = tile[tx][y];
+  }
+}
 
-  const double tol = sqrt(double(mr)) * Unit<T>::value;
-  const int npairs = ncp / 2;
-  int sweeps = 0;
-  bool converged = false;
-  for (int sw = 0; sw < max_sweeps; ++sw) {
-    if (threadIdx.x == 0) s_rot = 0;
-    __syncthreads();
-    int my_rot = 0;
-    for (int r = 0; r < ncp - 1; ++r) {
-      for (int q0 = wave * kPairBatch; q0 < npairs; q0 += kJacobiWaves * kPairBatch) {
-        int pi[kPairBatch], pj[kPairBatch];
-        bool live[kPairBatch];
-        T wi[kPairBatch][RPL], wj[kPairBatch][RPL], vi[kPairBatch][RPL], vj[kPairBatch][RPL];
+template <typename T, int B, int RPL>
+__global__ __launch_bounds__(kBjThreads) void bj_round_kernel(T* __restrict__ wbuf, int mr,
+                                                              int nbp, int round,
+                                                              BjCtl* __restrict__ ctl,
+                                                              double tol) {
+  constexpr int GL = kBjThreads / B;  // lanes per group
+  constexpr int CAP = GL * RPL;       // rows per column slot
+  __shared__ T s_x[B * CAP];
+  const int slice = blockIdx.y;
+  if (ctl[slice].state != 0) return;
+  int bi, bj;
+  rr_pair(nbp, round, blockIdx.x, bi, bj);
+  T* W = wbuf + int64_t(slice) * nbp * B * mr;
+  const int g = threadIdx.x / GL;
+  const int l = threadIdx.x % GL;
+  int nrot = 0;
+  bool bad = false;
+
+  // Rotation for the pair (x, y) (this lane's rows) from the group's sums.
+  auto angle = [&](const T (&x)[RPL], const T (&y)[RPL], double& c, double& s) {
+    T al = 0, be = 0, ga = 0;
 #pragma unroll
-        for (int b = 0; b < kPairBatch; ++b) {
-          const int q = q0 + b;
-          int i = 0, j = 0;
-          if (q < npairs) rr_pair(ncp, r, q, i, j);
-          live[b] = (q < npairs) && i < nc && j < nc;  // skip the dummy column
-          pi[b] = i;
-          pj[b] = j;
-#pragma unroll
-          for (int t = 0; t < RPL; ++t) {
-            const int row = lane + 64 * t;
-            const bool okw = live[b] && row < mr;
-            const bool okv = live[b] && row < nc;
-            wi[b][t] = okw ? W[int64_t(i) * mr + row] : T(0);
-            wj[b][t] = okw ? W[int64_t(j) * mr + row] : T(0);
-            vi[b][t] = okv ? V[int64_t(i) * nc + row] : T(0);
-            vj[b][t] = okv ? V[int64_t(j) * nc + row] : T(0);
-          }
-        }
-#pragma unroll
-        for (int b = 0; b < kPairBatch; ++b) {
-          double al = 0, be = 0, ga = 0;
-#pragma unroll
-          for (int t = 0; t < RPL; ++t) {
-            const double x = double(wi[b][t]), y = double(wj[b][t]);
-            al = fma(x, x, al);
-            be = fma(y, y, be);
-            ga = fma(x, y, ga);
-          }
-          al = wave_sum(al);
-          be = wave_sum(be);
-          ga = wave_sum(ga);
-          if (!live[b]) continue;
-          double c, s;
-          const int flag = rotation(al, be, ga, tol, c, s);
-          if (flag == 2) {
-            if (lane == 0) s_bad = 1;
-            continue;
-          }
-          if (flag == 0) continue;
-          ++my_rot;
-#pragma unroll
-          for (int tt = 0; tt < RPL; ++tt) {
-            const int row = lane + 64 * tt;
-            const double x = double(wi[b][tt]), y = double(wj[b][tt]);
-            if (row < mr) {
-              W[int64_t(pi[b]) * mr + row] = T(c * x - s * y);
-              W[int64_t(pj[b]) * mr + row] = T(s * x + c * y);
-            }
-            const double u = double(vi[b][tt]), v = double(vj[b][tt]);
-            if (row < nc) {
-              V[int64_t(pi[b]) * nc + row] = T(c * u - s * v);
-              V[int64_t(pj[b]) * nc + row] = T(s * u + c * v);
-            }
-          }
-        }
-      }
-      __syncthreads();  // the next round reads columns written in this one
+    for (int t = 0; t < RPL; ++t) {
+      al = fma(x[t], x[t], al);
+      be = fma(y[t], y[t], be);
+      ga = fma(x[t], y[t], ga);
     }
-    if (lane == 0 && my_rot) atomicAdd(&s_rot, my_rot);
-    __syncthreads();
-    sweeps = sw + 1;
-    const bool done = (s_rot == 0);
-    const bool bad = (s_bad != 0);
-    __syncthreads();
-    if (bad) break;
-    if (done) {
-      converged = true;
-      break;
+    al = group_sum<GL>(al);
+    be = group_sum<GL>(be);
+    ga = group_sum<GL>(ga);
+    const int f = rotation(double(al), double(be), double(ga), tol, c, s);
+    nrot += f == 1;
+    bad |= f == 2;
+  };
+
+  T top[RPL], bot[RPL];
+  if (round == 0) {
+    // Pairs inside each block, J first then I: columns in LDS slots, B / 2
+    // groups rotate one pair each per sub-round.
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+      const T* src = W + int64_t((blk == 0 ? bj : bi) * B + g) * mr;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int row = l + GL * t;
+        s_x[g * CAP + GL * t + l] = row < mr ? src[row] : T(0);
+      }
+      __syncthreads();
+      for (int r = 0; r < B - 1; ++r) {
+        if (g < B / 2) {
+          int i, j;
+          rr_pair(B, r, g, i, j);
+          T x[RPL], y[RPL];
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) {
+            x[t] = s_x[i * CAP + GL * t + l];
+            y[t] = s_x[j * CAP + GL * t + l];
+          }
+          double c, s;
+          angle(x, y, c, s);
+          const T ct = T(c), st = T(s);
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) {
+            s_x[i * CAP + GL * t + l] = ct * x[t] - st * y[t];
+            s_x[j * CAP + GL * t + l] = st * x[t] + ct * y[t];
+          }
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        if (blk == 0)
+          bot[t] = s_x[g * CAP + GL * t + l];
+        else
+          top[t] = s_x[g * CAP + GL * t + l];
+      }
+      __syncthreads();
+    }
+  } else {
+    const T* ti = W + int64_t(bi * B + g) * mr;
+    const T* tj = W + int64_t(bj * B + g) * mr;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int row = l + GL * t;
+      top[t] = row < mr ? ti[row] : T(0);
+      bot[t] = row < mr ? tj[row] : T(0);
     }
   }
 
-  emit_factors<T>(W, V, d, slice, uhat, shat, vhat, us, s_sigma, s_order);
-  if (threadIdx.x == 0) info[slice] = (converged && s_bad == 0) ? sweeps : -sweeps;
+  // Cross pairs: group g holds column g of block bi and, in sub-round t,
+  // column (g + t) mod B of block bj.
+  for (int sub = 0; sub < B; ++sub) {
+    double c, s;
+    angle(top, bot, c, s);
+    const T ct = T(c), st = T(s);
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const T x = top[t], y = bot[t];
+      top[t] = ct * x - st * y;
+      bot[t] = st * x + ct * y;
+    }
+    if (sub + 1 < B) {
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) s_x[g * CAP + GL * t + l] = bot[t];
+      __syncthreads();
+      const int from = (g + 1) % B;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) bot[t] = s_x[from * CAP + GL * t + l];
+      __syncthreads();
+    }
+  }
+  T* di = W + int64_t(bi * B + g) * mr;
+  T* dj = W + int64_t(bj * B + (g + B - 1) % B) * mr;
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int row = l + GL * t;
+    if (row < mr) {
+      di[row] = top[t];
+      dj[row] = bot[t];
+    }
+  }
+  if (l == 0 && nrot > 0) atomicAdd(&ctl[slice].rot, nrot);
+  if (l == 0 && bad) atomicOr(&ctl[slice].bad, 1);
+}
+
+// End of a sweep: count it and decide whether each slice goes on.
+__global__ __launch_bounds__(256) void bj_sweep_end_kernel(BjCtl* __restrict__ ctl, int nsl,
+                                                           int max_sweeps) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= nsl) return;
+  BjCtl c = ctl[s];
+  if (c.state != 0) return;
+  c.sweeps += 1;
+  if (c.bad)
+    c.state = 2;
+  else if (c.rot == 0)
+    c.state = 1;
+  else if (c.sweeps >= max_sweeps)
+    c.state = 3;
+  c.rot = 0;
+  ctl[s] = c;
+}
+
+// Singular values, ranking and the factor taken from W, per slice.
+template <typename T>
+__global__ __launch_bounds__(kJacobiThreads) void bj_emit_kernel(
+    const T* __restrict__ wbuf, SvdDims d, int ncb, const BjCtl* __restrict__ ctl,
+    T* __restrict__ uhat, T* __restrict__ shat, T* __restrict__ vhat, T* __restrict__ us,
+    int32_t* __restrict__ info) {
+  __shared__ double s_sigma[kMaxSide];
+  __shared__ int s_order[kMaxSide];
+  const int slice = blockIdx.x;
+  emit_factors<T>(wbuf + int64_t(slice) * ncb * d.mr, d, slice, uhat, shat, vhat, us, s_sigma,
+                  s_order);
+  if (threadIdx.x == 0) {
+    const BjCtl c = ctl[slice];
+    info[slice] = c.state == 1 ? c.sweeps : -(c.sweeps > 0 ? c.sweeps : 1);
+  }
 }
 
 // Cross-lane moves inside rows of 16 lanes.  CTRL is a DPP control word; all
@@ -627,7 +736,7 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
     }
   }
   __syncthreads();
-  emit_factors<T>(W, static_cast<const T*>(nullptr), d, slice, uhat, shat, vhat, us, s_sigma,
+  emit_factors<T>(W, d, slice, uhat, shat, vhat, us, s_sigma,
                   s_order);
   if (threadIdx.x == 0) info[slice] = converged ? sw : -sw;
 }
@@ -652,7 +761,8 @@ __global__ __launch_bounds__(256) void recover_kernel(const T* __restrict__ ah, 
   T* Vo = vhat + int64_t(slice) * d.n2 * k;
   const T* src = d.trans ? Vo : U;  // the column formed from W, mr entries
   T* dst = d.trans ? U : Vo;        // the column recovered here, nc entries
-  __shared__ double s_src[1024];
+  constexpr int kOut = kMaxSide / 256;
+  __shared__ double s_src[kMaxSide];
   __shared__ double s_best[256];
   __shared__ int s_row[256];
   __shared__ double s_val[256];
@@ -660,11 +770,11 @@ __global__ __launch_bounds__(256) void recover_kernel(const T* __restrict__ ah, 
   const double inv = sg > 0 ? 1.0 / sg : 0.0;
   for (int t = threadIdx.x; t < mr; t += 256) s_src[t] = double(src[int64_t(t) * k + i]);
   __syncthreads();
-  double out[4];
+  double out[kOut];
   double best = -1.0, bval = 0.0;
   int brow = 0x7fffffff;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < kOut; ++j) {
     const int r = threadIdx.x + 256 * j;
     double acc = 0;
     if (r < nc) {
@@ -703,7 +813,7 @@ __global__ __launch_bounds__(256) void recover_kernel(const T* __restrict__ ah, 
     sgn = s_val[0] < 0 ? -1.0 : 1.0;
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < kOut; ++j) {
     const int r = threadIdx.x + 256 * j;
     if (r < nc) {
       const T x = T(sgn * out[j]);
@@ -842,8 +952,33 @@ __global__ __launch_bounds__(256) void max_reduce_kernel(const double* __restric
   if (threadIdx.x == 0) *out = red[0];
 }
 
+// Which Jacobi kernel a slice shape takes.  Register-resident kernel when the
+// columns fit: each of up to 32 units (16-lane rows) owns J slots, J the
+// smallest power of two with 32 * J >= nc_pad / 2, rpl rows per lane; the
+// block kernel otherwise.
+struct JacobiChoice {
+  bool reg;
+  int J, nunits, rpl;
+  BjShape bj;
+};
+
+inline JacobiChoice choose_jacobi(int mr, int nc, size_t es) {
+  JacobiChoice c{};
+  int ncp = nc + (nc & 1);
+  if (ncp < 2) ncp = 2;
+  const int half = ncp / 2;
+  c.J = 1;
+  while (c.J * kUnits < half) c.J *= 2;
+  c.nunits = (half + c.J - 1) / c.J;
+  c.rpl = 1;
+  while (c.rpl * 16 < mr) c.rpl *= 2;
+  c.reg = c.rpl <= 16 && c.J <= 4 && (es == 4 || (c.rpl <= 8 && c.J * c.rpl <= 16));
+  c.bj = bj_shape(mr, nc);
+  return c;
+}
+
 struct SvdPlan {
-  size_t ah, w, v, us, part, total;
+  size_t ah, w, us, ctl, part, total;
 };
 
 // p coefficient slices are lifted; the first nsl of them are decomposed
@@ -851,6 +986,8 @@ struct SvdPlan {
 inline SvdPlan plan_svd(int64_t n1, int64_t n2, int64_t p, int64_t nsl, int k, size_t es) {
   const int64_t mr = n1 > n2 ? n1 : n2;
   const int64_t nc = n1 > n2 ? n2 : n1;
+  const JacobiChoice jc = choose_jacobi(int(mr), int(nc), es);
+  const int64_t ncw = jc.reg ? nc : int64_t(jc.bj.nbp) * jc.bj.B;  // columns of W
   SvdPlan pl{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -859,9 +996,9 @@ inline SvdPlan plan_svd(int64_t n1, int64_t n2, int64_t p, int64_t nsl, int k, s
     return at;
   };
   pl.ah = take(size_t(p * n1 * n2) * es);  // coefficients, later the rebuilt ones
-  pl.w = take(size_t(nsl * nc * mr) * es);
-  pl.v = take(size_t(nsl * nc * nc) * es);
+  pl.w = take(size_t(nsl * ncw * mr) * es);
   pl.us = take(size_t(nsl * n1 * k) * es);
+  pl.ctl = take(size_t(nsl) * sizeof(BjCtl));
   pl.part = take(size_t(nsl) * 2 * sizeof(double));
   pl.total = off + 256;
   return pl;
@@ -886,8 +1023,8 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
   char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
   T* ah = reinterpret_cast<T*>(base + pl.ah);
   T* w = reinterpret_cast<T*>(base + pl.w);
-  T* v = reinterpret_cast<T*>(base + pl.v);
   T* us = reinterpret_cast<T*>(base + pl.us);
+  BjCtl* ctl = reinterpret_cast<BjCtl*>(base + pl.ctl);
   double* part = reinterpret_cast<double*>(base + pl.part);
 
   hipError_t e;
@@ -910,19 +1047,11 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
   d.trans = n1 < n2 ? 1 : 0;
   if (max_sweeps <= 0) max_sweeps = sizeof(T) == 8 ? 30 : 20;
 
-  const dim3 grid{unsigned(nsl)};
-  const dim3 block{unsigned(kJacobiThreads)};
-  // Register-resident kernel when the columns fit: each of up to 32 units
-  // (16-lane rows) owns J slots, J the smallest power of two with
-  // 32 * J >= nc_pad / 2; RPL = rows per lane.
-  const int half = d.ncp / 2;
-  int J = 1;
-  while (J * kUnits < half) J *= 2;
-  const int nunits = (half + J - 1) / J;
-  int rpl = 1;
-  while (rpl * 16 < d.mr) rpl *= 2;
-  const bool reg_ok = rpl <= 16 && J <= 4 && (sizeof(T) == 4 || (rpl <= 8 && J * rpl <= 16));
-  if (reg_ok) {
+  const JacobiChoice jc = choose_jacobi(d.mr, d.nc, sizeof(T));
+  if (jc.reg) {
+    const dim3 grid{unsigned(nsl)};
+    const dim3 block{unsigned(kJacobiThreads)};
+    const int J = jc.J, rpl = jc.rpl, nunits = jc.nunits;
 #define WP_JREG(JJ, RR)                                                                        \
   if (J == JJ && rpl == RR)                                                                    \
     hipLaunchKernelGGL((jacobi_reg_kernel<T, JJ, RR>), grid, block, 0, s, ah, w, d, nunits,     \
@@ -934,21 +1063,46 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
       WP_JREG(1, 16) WP_JREG(2, 16) WP_JREG(4, 8) WP_JREG(4, 16)
     }
 #undef WP_JREG
+  } else {
+    const BjShape b = jc.bj;
+    const int ncb = b.nbp * b.B;
+    hipLaunchKernelGGL((bj_init_kernel<T>),
+                       dim3(unsigned((d.mr + 31) / 32), unsigned((ncb + 31) / 32), unsigned(nsl)),
+                       dim3(256), 0, s, ah, w, d, ncb);
+    const int64_t nctl = nsl * int64_t(sizeof(BjCtl) / sizeof(int));
+    hipLaunchKernelGGL((zero_kernel<int>), dim3(unsigned((nctl + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<int*>(ctl), nctl);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((recover_kernel<T>), dim3(unsigned(nsl * k)), dim3(256), 0, s, ah, d, uhat,
-                       shat, vhat, us);
-  } else if (d.mr <= 64) {
-    hipLaunchKernelGGL((jacobi_global_kernel<T, 1>), grid, block, 0, s, ah, w, v, d, max_sweeps, uhat, shat, vhat, us, info);
-  } else if (d.mr <= 128) {
-    hipLaunchKernelGGL((jacobi_global_kernel<T, 2>), grid, block, 0, s, ah, w, v, d, max_sweeps, uhat, shat, vhat, us, info);
-  } else if (d.mr <= 256) {
-    hipLaunchKernelGGL((jacobi_global_kernel<T, 4>), grid, block, 0, s, ah, w, v, d, max_sweeps, uhat, shat, vhat, us, info);
-  } else if (d.mr <= 512) {
-    hipLaunchKernelGGL((jacobi_global_kernel<T, 8>), grid, block, 0, s, ah, w, v, d, max_sweeps, uhat, shat, vhat, us, info);
-  } else {
-    hipLaunchKernelGGL((jacobi_global_kernel<T, 16>), grid, block, 0, s, ah, w, v, d, max_sweeps, uhat, shat, vhat, us, info);
+    const double tol = sqrt(double(d.mr)) * Unit<T>::value;
+    const dim3 rgrid{unsigned(b.nbp / 2), unsigned(nsl)};
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+      for (int r = 0; r + 1 < b.nbp; ++r) {
+        bool launched = false;
+#define WP_BJ(BB, RR)                                                                          \
+  if (b.B == BB && b.rpl == RR) {                                                              \
+    hipLaunchKernelGGL((bj_round_kernel<T, BB, RR>), rgrid, dim3(kBjThreads), 0, s, w, d.mr,    \
+                       b.nbp, r, ctl, tol);                                                    \
+    launched = true;                                                                           \
   }
+        WP_BJ(16, 4) WP_BJ(16, 8) WP_BJ(16, 12) WP_BJ(16, 16)
+        WP_BJ(16, 20) WP_BJ(16, 24) WP_BJ(16, 28) WP_BJ(16, 32)
+        WP_BJ(8, 20) WP_BJ(8, 24) WP_BJ(8, 28) WP_BJ(8, 32)
+#undef WP_BJ
+        if (!launched) return hipErrorInvalidValue;  // shape outside the instantiated set
+      }
+      hipLaunchKernelGGL(bj_sweep_end_kernel, dim3(unsigned((nsl + 255) / 256)), dim3(256), 0, s,
+                         ctl, int(nsl), max_sweeps);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((bj_emit_kernel<T>), dim3(unsigned(nsl)), dim3(kJacobiThreads), 0, s, w, d,
+                       ncb, ctl, uhat, shat, vhat, us, info);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((recover_kernel<T>), dim3(unsigned(nsl * k)), dim3(256), 0, s, ah, d, uhat,
+                     shat, vhat, us);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
 
@@ -980,7 +1134,7 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
     if (e != hipSuccess) return e;
   }
 
-  if (polish && reg_ok && k <= 64) {
+  if (polish && k <= 64) {
     // Orthonormalise the recovered factor (after the rebuild, which uses the
     // recovered columns as they are: their product with U is the exact rank-k
     // projection U U^T A).

@@ -124,7 +124,7 @@ def test_svd_validation(lib):
     need = lib.w_svd_workspace(8, 6, 16, 2, 3, 1)
     assert need > 0
     assert lib.w_svd_workspace(8, 6, 16, 2, 7, 1) == 0           # k > min(n1, n2)
-    assert lib.w_svd_workspace(2048, 6, 16, 2, 3, 1) == 0        # n1 > 1024
+    assert lib.w_svd_workspace(2049, 6, 16, 2, 3, 1) == 0        # n1 > 2048
     f = lib.w_svd
     U, S, V, AK = (ctypes.c_void_p(0x500000), ctypes.c_void_p(0x600000),
                    ctypes.c_void_p(0x700000), ctypes.c_void_p(0x800000))
@@ -166,7 +166,7 @@ def test_pinv_validation(lib):
     assert 0 < lib.w_pinv_workspace(8, 6, 16, 2, 1, 1) < need     # sparse: 8 of 16 slices
     assert lib.w_pinv_workspace(8, 6, 16, 0, 1, 1) == 0            # sparse needs L >= 1
     assert lib.w_pinv_workspace(8, 6, 12, 3, 0, 1) == 0            # p not divisible by 2^L
-    assert lib.w_pinv_workspace(1100, 6, 16, 2, 0, 1) == 0         # n1 > 1024
+    assert lib.w_pinv_workspace(2100, 6, 16, 2, 0, 1) == 0         # n1 > 2048
     assert lib.w_pinv_workspace(8, 6, 16, 2, 0, 2) == 0            # bad dtype code
     f = lib.w_pinv
     OUT, INFO = ctypes.c_void_p(0x500000), ctypes.c_void_p(0x900000)

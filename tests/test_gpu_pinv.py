@@ -37,10 +37,12 @@ def _kappa(a, L):
 
 
 @pytest.mark.parametrize("shape,L", [((16, 40, 24), 2), ((16, 24, 40), 2), ((8, 9, 9), 3),
-                                     ((4, 130, 70), 1), ((2, 300, 20), 1), ((4, 1, 6), 2)])
+                                     ((4, 130, 70), 1), ((2, 300, 20), 1), ((4, 1, 6), 2),
+                                     ((2, 700, 650), 1), ((2, 45, 1500), 1)])
 def test_pinv_f64_shapes(wp, shape, L):
-    # Both orientations (n1 < n2 runs on the transpose), square, a slice with
-    # more than 128 rows (the workspace Jacobi kernel in FP64), a single row.
+    # Both orientations (n1 < n2 runs on the transpose), square, slices with
+    # more than 128 rows (the block Jacobi kernel in FP64; 1500 rows take its
+    # 8-column blocks), a single row.
     import torch
     a = np.random.default_rng(sum(shape)).standard_normal(shape)
     out, info = wp.w_pinv(to_dev(a, torch.float64), L)

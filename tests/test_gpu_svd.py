@@ -107,7 +107,8 @@ def test_nonfinite_input_terminates(wp):
     assert info[1] > 0 and info[3] > 0
 
 
-@pytest.mark.parametrize("shape,k", [((16, 100, 60), 10), ((8, 33, 64), 8), ((4, 256, 256), 20)])
+@pytest.mark.parametrize("shape,k", [((16, 100, 60), 10), ((8, 33, 64), 8), ((4, 256, 256), 20),
+                                     ((4, 600, 300), 20), ((4, 1200, 90), 12)])
 def test_f32_shapes(wp, shape, k):
     import torch
     p, n1, n2 = shape
