@@ -206,6 +206,54 @@ __device__ void emit_factors(const T* __restrict__ W, const SvdDims& d, int slic
   }
 }
 
+// Cross-lane moves inside rows of 16 lanes.  CTRL is a DPP control word; all
+// controls used here read a valid lane, so the moves need no old value.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float x) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_move(T x) {
+  if constexpr (sizeof(T) == 8)
+    return dpp_f64<CTRL>(x);
+  else
+    return dpp_f32<CTRL>(x);
+}
+
+// Sum over the 16 lanes of a row: rotate by 8 and by 4 inside the row, then
+// swap pairs of 2 and of 1 inside quads.  Each step adds two values in both
+// partner lanes (a + b and b + a), so all 16 lanes end with the same bits.
+// In FP32 the move is fused into the add (v_add_f32 with DPP).
+template <typename T>
+__device__ __forceinline__ T row_sum16(T x) {
+  x += dpp_move<0x128>(x);  // row_ror:8
+  x += dpp_move<0x124>(x);  // row_ror:4
+  x += dpp_move<0x4e>(x);   // quad_perm [2,3,0,1]
+  x += dpp_move<0xb1>(x);   // quad_perm [1,0,3,2]
+  return x;
+}
+
+// Value of lane L of the row, in every lane of the row (row_newbcast).
+template <int L, typename T>
+__device__ __forceinline__ T row_bcast(T x) {
+  return dpp_move<0x150 + L>(x);
+}
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
 // ---- Block one-sided Jacobi (slices beyond the register-resident kernel) ----
 // W (mr x nc, column c at W + c * mr) is padded with zero columns to
 // nbp * B columns, grouped in nbp blocks of B.  A sweep is a round-robin
@@ -230,6 +278,8 @@ struct BjCtl {
   int sweeps;  // sweeps completed
   int rot;     // rotations in the current sweep
   int bad;     // non-finite value seen in the current sweep
+  int live;    // the slice has a nonzero entry (a zero slice needs no rotation)
+  int pad[3];
 };
 
 // Block width and rows per lane of the block kernel for mr rows.
@@ -246,24 +296,53 @@ inline BjShape bj_shape(int mr, int nc) {
   return s;
 }
 
-template <int GL>
-__device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int o = GL / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// Sum over an aligned group of GL = 32 or 64 lanes, the same bits in every
+// lane: 16-lane row sums (DPP), then the partner row (permlane16_swap) and
+// for 64 lanes the partner half (permlane32_swap).  With a = b = x a swap
+// leaves the even (lower) part's value in a and the odd (upper) part's in b
+// on both sides, so every lane adds the two in the same order.
+template <bool HALF>
+__device__ __forceinline__ void swap_parts(unsigned& a, unsigned& b) {
+  if constexpr (HALF) {
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+  }
 }
-template <int GL>
-__device__ __forceinline__ float group_sum(float v) {
-#pragma unroll
-  for (int o = GL / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+template <bool HALF>
+__device__ __forceinline__ double pair_sum(double x) {
+  unsigned lo0 = unsigned(__double2loint(x)), hi0 = unsigned(__double2hiint(x));
+  unsigned lo1 = lo0, hi1 = hi0;
+  swap_parts<HALF>(lo0, lo1);
+  swap_parts<HALF>(hi0, hi1);
+  return __hiloint2double(int(hi0), int(lo0)) + __hiloint2double(int(hi1), int(lo1));
+}
+template <bool HALF>
+__device__ __forceinline__ float pair_sum(float x) {
+  unsigned a = __builtin_bit_cast(unsigned, x), b = a;
+  swap_parts<HALF>(a, b);
+  return __builtin_bit_cast(float, a) + __builtin_bit_cast(float, b);
+}
+template <int GL, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+  static_assert(GL == 32 || GL == 64, "group of 32 or 64 lanes");
+  v = row_sum16<T>(v);
+  v = pair_sum<false>(v);
+  if constexpr (GL == 64) v = pair_sum<true>(v);
   return v;
 }
 
 // Copies the slices into column-major W through 32 x 32 LDS tiles (coalesced
-// on both sides for either orientation) and zeroes the padding columns.
+// on both sides for either orientation), zeroes the padding columns and marks
+// the slices that have a nonzero entry.
 template <typename T>
 __global__ __launch_bounds__(256) void bj_init_kernel(const T* __restrict__ ah,
-                                                      T* __restrict__ wbuf, SvdDims d, int ncb) {
+                                                      T* __restrict__ wbuf, SvdDims d, int ncb,
+                                                      BjCtl* __restrict__ ctl) {
   __shared__ T tile[32][33];
   const int slice = blockIdx.z;
   const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
@@ -282,10 +361,14 @@ __global__ __launch_bounds__(256) void bj_init_kernel(const T* __restrict__ ah,
     }
   }
   __syncthreads();
+  bool nz = false;
   for (int y = ty; y < 32; y += 8) {
     const int r = r0 + tx, c = c0 + y;
-    if (r < d.mr && c < ncb) W[int64_t(c) * d.mr + r] = tile[tx][y];
+    const T v = tile[tx][y];
+    nz |= v != T(0);  // NaN counts as nonzero
+    if (r < d.mr && c < ncb) W[int64_t(c) * d.mr + r] = v;
   }
+  if (__syncthreads_or(nz) && threadIdx.x == 0) atomicOr(&ctl[slice].live, 1);
 }
 
 template <typename T, int B, int RPL>
@@ -297,7 +380,7 @@ __global__ __launch_bounds__(kBjThreads) void bj_round_kernel(T* __restrict__ wb
   constexpr int CAP = GL * RPL;       // rows per column slot
   __shared__ T s_x[B * CAP];
   const int slice = blockIdx.y;
-  if (ctl[slice].state != 0) return;
+  if (ctl[slice].state != 0 || !ctl[slice].live) return;
   int bi, bj;
   rr_pair(nbp, round, blockIdx.x, bi, bj);
   T* W = wbuf + int64_t(slice) * nbp * B * mr;
@@ -445,54 +528,6 @@ __global__ __launch_bounds__(kJacobiThreads) void bj_emit_kernel(
   if (threadIdx.x == 0) {
     const BjCtl c = ctl[slice];
     info[slice] = c.state == 1 ? c.sweeps : -(c.sweeps > 0 ? c.sweeps : 1);
-  }
-}
-
-// Cross-lane moves inside rows of 16 lanes.  CTRL is a DPP control word; all
-// controls used here read a valid lane, so the moves need no old value.
-template <int CTRL>
-__device__ __forceinline__ float dpp_f32(float x) {
-  return __builtin_bit_cast(
-      float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xf, 0xf, true));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double x) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, true);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, true);
-  return __hiloint2double(hi, lo);
-}
-template <int CTRL, typename T>
-__device__ __forceinline__ T dpp_move(T x) {
-  if constexpr (sizeof(T) == 8)
-    return dpp_f64<CTRL>(x);
-  else
-    return dpp_f32<CTRL>(x);
-}
-
-// Sum over the 16 lanes of a row: rotate by 8 and by 4 inside the row, then
-// swap pairs of 2 and of 1 inside quads.  Each step adds two values in both
-// partner lanes (a + b and b + a), so all 16 lanes end with the same bits.
-// In FP32 the move is fused into the add (v_add_f32 with DPP).
-template <typename T>
-__device__ __forceinline__ T row_sum16(T x) {
-  x += dpp_move<0x128>(x);  // row_ror:8
-  x += dpp_move<0x124>(x);  // row_ror:4
-  x += dpp_move<0x4e>(x);   // quad_perm [2,3,0,1]
-  x += dpp_move<0xb1>(x);   // quad_perm [1,0,3,2]
-  return x;
-}
-
-// Value of lane L of the row, in every lane of the row (row_newbcast).
-template <int L, typename T>
-__device__ __forceinline__ T row_bcast(T x) {
-  return dpp_move<0x150 + L>(x);
-}
-
-template <int I, int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (I < N) {
-    f(std::integral_constant<int, I>{});
-    static_for<I + 1, N>(f);
   }
 }
 
@@ -1066,12 +1101,12 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
   } else {
     const BjShape b = jc.bj;
     const int ncb = b.nbp * b.B;
-    hipLaunchKernelGGL((bj_init_kernel<T>),
-                       dim3(unsigned((d.mr + 31) / 32), unsigned((ncb + 31) / 32), unsigned(nsl)),
-                       dim3(256), 0, s, ah, w, d, ncb);
     const int64_t nctl = nsl * int64_t(sizeof(BjCtl) / sizeof(int));
     hipLaunchKernelGGL((zero_kernel<int>), dim3(unsigned((nctl + 255) / 256)), dim3(256), 0, s,
                        reinterpret_cast<int*>(ctl), nctl);
+    hipLaunchKernelGGL((bj_init_kernel<T>),
+                       dim3(unsigned((d.mr + 31) / 32), unsigned((ncb + 31) / 32), unsigned(nsl)),
+                       dim3(256), 0, s, ah, w, d, ncb, ctl);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const double tol = sqrt(double(d.mr)) * Unit<T>::value;
