@@ -1050,7 +1050,7 @@ __global__ __launch_bounds__(256) void zero_kernel(T* __restrict__ x, int64_t n)
 template <typename T>
 hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, bool sparse,
                    T* uhat, T* shat, T* vhat, T* ak, int max_sweeps, int32_t* info,
-                   double* orth_err, void* ws, hipStream_t s, bool polish = true) {
+                   double* orth_err, void* ws, hipStream_t s, bool second_factor = true) {
   // sp-w-svd decomposes only s_L and d_L, the leading 2 p / 2^L coefficient
   // slices; the finer details are dropped (zero) in the rebuild.
   const int64_t nsl = sparse ? 2 * (p >> L) : p;
@@ -1135,7 +1135,7 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
                        ncb, ctl, uhat, shat, vhat, us, info);
   }
   e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !second_factor) return e;
   hipLaunchKernelGGL((recover_kernel<T>), dim3(unsigned(nsl * k)), dim3(256), 0, s, ah, d, uhat,
                      shat, vhat, us);
   e = hipGetLastError();
@@ -1169,7 +1169,7 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
     if (e != hipSuccess) return e;
   }
 
-  if (polish && k <= 64) {
+  if (k <= 64) {
     // Orthonormalise the recovered factor (after the rebuild, which uses the
     // recovered columns as they are: their product with U is the exact rank-k
     // projection U U^T A).
@@ -1194,18 +1194,21 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
 // Pseudo-inverse of sigma applied to the columns of vhat (n2 x k per slice):
 // column i is scaled by 1 / sigma_i when sigma_i > rtol * sigma_max, else
 // zeroed (Def. 2.6 per coefficient slice; sigma is sorted, sigma_max first).
+// x_i <- x_i / sigma_i^2 for sigma_i > rtol * sigma_0, else 0, for the k
+// columns of each slice of x (rows x k); grid (x, nsl).
 template <typename T>
-__global__ __launch_bounds__(256) void pinv_scale_kernel(T* __restrict__ v,
-                                                         const T* __restrict__ sh, int n2, int k,
+__global__ __launch_bounds__(256) void pinv_scale_kernel(T* __restrict__ x,
+                                                         const T* __restrict__ sh, int rows, int k,
                                                          double rtol) {
   const int64_t slice = blockIdx.y;
   const T* sg = sh + slice * k;
   const double cut = rtol * double(sg[0]);
-  T* vs = v + slice * n2 * k;
-  for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < int64_t(n2) * k;
+  T* xs = x + slice * rows * k;
+  for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < int64_t(rows) * k;
        e += int64_t(gridDim.x) * 256) {
     const double si = double(sg[e % k]);
-    vs[e] = si > cut ? T(double(vs[e]) / si) : T(0);
+    const double inv = si > cut ? 1.0 / si : 0.0;
+    xs[e] = T(double(xs[e]) * inv * inv);
   }
 }
 
@@ -1232,13 +1235,14 @@ inline PinvPlan plan_pinv(int64_t n1, int64_t n2, int64_t p, int64_t nsl, size_t
   return pl;
 }
 
-// A^+ = W^{-1}( Vhat_c Sigma_c^+ Uhat_c^T ) over the coefficient slices c (all
-// p, or only s_L and d_L when sparse; the rest of the coefficients are zero).
-// The recovered factor is used as recovered (no polish): with U from the
-// Jacobi columns and V = A^T U / sigma, V Sigma^+ U^T = A^T U Sigma^-2 U^T over
-// the kept values, which is A^+ for any U that spans the kept space.  A polish
-// step would mix the arbitrary columns of values under the cut (rank-deficient
-// slices) into the kept ones.
+// A^+ = W^{-1}( P_c ) over the coefficient slices c (all p, or only s_L and
+// d_L when sparse; the rest of the coefficients are zero).  Per slice A_c the
+// Jacobi gives the factor F formed by W and sigma; with the cut values
+// dropped, P_c = V Sigma^+ U^T is
+//   A_c^T U Sigma^-2 U^T = (A_c^T F) (F Sigma^-2)^T      when n1 >= n2 (F = U),
+//   V Sigma^-2 V^T A_c^T = (F Sigma^-2) (A_c F)^T        when n1 < n2 (F = V),
+// two face-products on the matrix cores, with no recovered factor.  Both
+// forms are exact for any F that spans the kept space.
 template <typename T>
 hipError_t run_pinv(const T* a, T* out, int64_t n1, int64_t n2, int64_t p, int L, bool sparse,
                     double rtol, int32_t* info, void* ws, hipStream_t s) {
@@ -1250,13 +1254,35 @@ hipError_t run_pinv(const T* a, T* out, int64_t n1, int64_t n2, int64_t p, int L
   T* sh = reinterpret_cast<T*>(base + pl.sh);
   T* vh = reinterpret_cast<T*>(base + pl.vh);
   T* ph = reinterpret_cast<T*>(base + pl.ph);
+  // The coefficient slices, lifted by run_svd into its own workspace region.
+  const T* ah = reinterpret_cast<const T*>(base + pl.svd +
+                                           plan_svd(n1, n2, p, nsl, int(k), sizeof(T)).ah);
   hipError_t e = run_svd<T>(a, n1, n2, p, L, int(k), sparse, uh, sh, vh, static_cast<T*>(nullptr),
-                            0, info, nullptr, base + pl.svd, s, /*polish=*/false);
+                            0, info, nullptr, base + pl.svd, s, /*second_factor=*/false);
   if (e != hipSuccess) return e;
-  const int64_t per = n2 * k;
-  const int64_t want = (per + 255) / 256;
+  const bool trans = n1 < n2;
+  // M = A^T U into vh (n2 x k), or A V into uh (n1 x k).
+  if constexpr (sizeof(T) == 8) {
+    e = trans ? launch_face_f64(reinterpret_cast<const double*>(ah),
+                                reinterpret_cast<const double*>(vh), reinterpret_cast<double*>(uh),
+                                n1, n2, k, nsl, false, false, s)
+              : launch_face_f64(reinterpret_cast<const double*>(ah),
+                                reinterpret_cast<const double*>(uh), reinterpret_cast<double*>(vh),
+                                n2, n1, k, nsl, true, false, s);
+  } else {
+    e = trans ? launch_face_f32(reinterpret_cast<const float*>(ah),
+                                reinterpret_cast<const float*>(vh), reinterpret_cast<float*>(uh),
+                                n1, n2, k, nsl, false, false, s)
+              : launch_face_f32(reinterpret_cast<const float*>(ah),
+                                reinterpret_cast<const float*>(uh), reinterpret_cast<float*>(vh),
+                                n2, n1, k, nsl, true, false, s);
+  }
+  if (e != hipSuccess) return e;
+  // F Sigma^-2 in place (F = uh or vh).
+  const int64_t rows = trans ? n2 : n1;
+  const int64_t want = (rows * k + 255) / 256;
   hipLaunchKernelGGL((pinv_scale_kernel<T>), dim3(unsigned(want < 64 ? want : 64), unsigned(nsl)),
-                     dim3(256), 0, s, vh, sh, int(n2), int(k), rtol);
+                     dim3(256), 0, s, trans ? vh : uh, sh, int(rows), int(k), rtol);
   if (nsl < p) {
     const int64_t tail = (p - nsl) * n2 * n1;
     const int64_t wt = (tail + 255) / 256;
@@ -1265,6 +1291,7 @@ hipError_t run_pinv(const T* a, T* out, int64_t n1, int64_t n2, int64_t p, int L
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
+  // P = vh uh^T (n2 x n1), then W^{-1}.
   if constexpr (sizeof(T) == 8) {
     e = launch_face_f64(reinterpret_cast<const double*>(vh), reinterpret_cast<const double*>(uh),
                         reinterpret_cast<double*>(ph), n2, k, n1, nsl, false, true, s);
