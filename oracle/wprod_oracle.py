@@ -30,7 +30,12 @@ Readings of the paper taken here (each listed in the design notes):
     (s_L and all d_j; the intermediate s_j, j < L, are not coefficients);
   * pseudo-inverse and truncated SVD act per coefficient slice (Thm 2.5,
     Thm 2.6 and Remark 2.2, whose printed values this reading reproduces);
-  * PSNR uses MPP^2 in the numerator; with data in [0, 1], MPP = 1.
+  * PSNR uses MPP^2 in the numerator; with data in [0, 1], MPP = 1;
+  * general lifting (Sec. II-A with chosen P_j, U_j; Remark 3.1): the
+    predicted entries are the first of each pair and the kept ones the second
+    (the odd and even entries of Alg. 1, whose indices are 1-based), so that
+    P_j = I, U_j = I/2 is exactly the lazy transform above; P_j and U_j are
+    5-tap stencils with the sequence extended by its end values.
 """
 
 import numpy as np
@@ -40,7 +45,10 @@ __all__ = [
     "face", "w_product", "w_product_vjp", "transpose", "identity", "inverse",
     "trace", "slice_svd", "w_svd", "w_svd_sparse", "spatial_factors", "w_pinv", "psnr",
     "lsq_grad", "deblur_gd", "coefficient_weights", "w_pinv_sparse", "toeplitz_blur",
-    "pinv_deblur",
+    "pinv_deblur", "SCHEME_TAPS", "scheme_operators", "lift_fwd_scheme", "lift_inv_scheme",
+    "scheme_matrix", "scheme_inverse_matrix", "lift_fwd_scheme_adj", "lift_inv_scheme_adj",
+    "w_product_scheme", "w_product_scheme_vjp", "lazy_scheme", "interpolating_scheme",
+    "cdf53_scheme",
 ]
 
 
@@ -418,3 +426,145 @@ def deblur_gd(k, y, L, steps, eta, x0=None):
     r = w_product(k, x, L) - y
     losses.append(float(np.sum(r * r)))
     return x, losses
+
+
+# ---- General predict / update lifting (Sec. II-A, W_j; Remark 3.1) -----------
+
+SCHEME_TAPS = 5   # stencil taps at offsets -2, -1, 0, 1, 2
+
+
+def _check_taps(taps, L):
+    taps = np.asarray(taps, dtype=np.float64)
+    if taps.shape != (L, 2, SCHEME_TAPS):
+        raise ValueError(f"taps must have shape ({L}, 2, {SCHEME_TAPS}), got {taps.shape}")
+    return taps
+
+
+def scheme_operators(n, pred, upd):
+    """P_j and U_j of one level as n x n matrices (n = pairs per tube).
+
+    P(e)[m] = sum_t pred[t] e[clamp(m + t - 2)] and U(d)[m] likewise, the
+    index clamped to [0, n - 1]: the sequence is extended by its end values.
+    """
+    P = np.zeros((n, n))
+    U = np.zeros((n, n))
+    for m in range(n):
+        for t in range(SCHEME_TAPS):
+            i = min(max(m + t - 2, 0), n - 1)
+            P[m, i] += pred[t]
+            U[m, i] += upd[t]
+    return P, U
+
+
+def _along0(mat, x):
+    """Apply the matrix to every mode-3 tube (axis 0) of x."""
+    return np.tensordot(mat, x, axes=(1, 0))
+
+
+def lift_fwd_scheme(x, L, taps):
+    """W_[L] with chosen predict and update operators (Sec. II-A, W_j).
+
+    taps[j-1] = (predict stencil, update stencil) of level j.  Each level takes
+    the first entry of every pair as o and the second as e, then
+    d_j = o - P_j e and s_j = e + U_j d_j.  Returns (s_L, d_L, ..., d_1).
+    """
+    x = np.asarray(x, dtype=np.float64)
+    check_levels(x.shape[0], L)
+    taps = _check_taps(taps, L)
+    s = x.copy()
+    details = []
+    for j in range(1, L + 1):
+        o = s[0::2]
+        e = s[1::2]
+        P, U = scheme_operators(e.shape[0], taps[j - 1, 0], taps[j - 1, 1])
+        d = o - _along0(P, e)
+        s = e + _along0(U, d)
+        details.append(d)
+    return np.concatenate([s] + details[::-1], axis=0)
+
+
+def lift_inv_scheme(c, L, taps):
+    """W_[L]^{-1} with chosen P_j, U_j (Sec. II-A, W_j^{-1}): for j = L down to
+    1, e = s_j - U_j d_j and o = d_j + P_j e, interleaved as (o, e) pairs."""
+    c = np.asarray(c, dtype=np.float64)
+    check_levels(c.shape[0], L)
+    taps = _check_taps(taps, L)
+    s, d = _split_coefficients(c, L)
+    s = s.copy()
+    for j in range(L, 0, -1):
+        P, U = scheme_operators(s.shape[0], taps[j - 1, 0], taps[j - 1, 1])
+        e = s - _along0(U, d[j])
+        o = d[j] + _along0(P, e)
+        nxt = np.empty((2 * s.shape[0],) + s.shape[1:], dtype=np.float64)
+        nxt[0::2] = o
+        nxt[1::2] = e
+        s = nxt
+    return s
+
+
+def scheme_matrix(p, L, taps):
+    """The p x p matrix of W_[L] (column i = W applied to the i-th unit tube)."""
+    return lift_fwd_scheme(np.eye(p), L, taps)
+
+
+def scheme_inverse_matrix(p, L, taps):
+    """The p x p matrix of W_[L]^{-1}, column by column from lift_inv_scheme."""
+    return lift_inv_scheme(np.eye(p), L, taps)
+
+
+def lift_fwd_scheme_adj(g, L, taps):
+    """W_[L]^T (not in the paper; the adjoint of Def. 2.1 needs it): the
+    transpose of the explicit matrix, applied to every tube."""
+    g = np.asarray(g, dtype=np.float64)
+    return _along0(scheme_matrix(g.shape[0], L, taps).T, g)
+
+
+def lift_inv_scheme_adj(g, L, taps):
+    """W_[L]^{-T}: the transpose of the explicit inverse matrix."""
+    g = np.asarray(g, dtype=np.float64)
+    return _along0(scheme_inverse_matrix(g.shape[0], L, taps).T, g)
+
+
+def w_product_scheme(a, b, L, taps, trans_a=False, trans_b=False):
+    """A *_w B (Def. 2.1) with the lifting of chosen P_j, U_j (Remark 3.1)."""
+    return lift_inv_scheme(face(lift_fwd_scheme(a, L, taps), lift_fwd_scheme(b, L, taps),
+                                trans_a, trans_b), L, taps)
+
+
+def w_product_scheme_vjp(a, b, g, L, taps):
+    """Reverse-mode derivative of C = A *_w B under a general scheme (chain rule
+    through Def. 2.1 with the explicit transposes)."""
+    ah = lift_fwd_scheme(a, L, taps)
+    bh = lift_fwd_scheme(b, L, taps)
+    gh = lift_inv_scheme_adj(g, L, taps)
+    da = lift_fwd_scheme_adj(face(gh, bh, trans_b=True), L, taps)
+    db = lift_fwd_scheme_adj(face(ah, gh, trans_a=True), L, taps)
+    return da, db
+
+
+def lazy_scheme(L):
+    """P_j = I, U_j = I/2 at every level: the lazy transform (Sec. II-A)."""
+    t = np.zeros((L, 2, SCHEME_TAPS))
+    t[:, 0, 2] = 1.0
+    t[:, 1, 2] = 0.5
+    return t
+
+
+def interpolating_scheme(L):
+    """Example 2.1: U_j = 0 and P_j the linear interpolate of the two kept
+    neighbours.  The predicted entry o[m] = f[2m] lies between e[m-1] = f[2m-1]
+    and e[m] = f[2m+1], so P(e)[m] = (e[m-1] + e[m]) / 2 (taps at -1 and 0)."""
+    t = np.zeros((L, 2, SCHEME_TAPS))
+    t[:, 0, 1] = 0.5
+    t[:, 0, 2] = 0.5
+    return t
+
+
+def cdf53_scheme(L):
+    """The interpolating predict with the update U(d)[m] = (d[m] + d[m+1]) / 4
+    (taps at 0 and +1): the kept entry e[m] = f[2m+1] lies between the predicted
+    o[m] and o[m+1].  This is the CDF 5/3 pair of lifting steps."""
+    t = interpolating_scheme(L)
+    t[:, 1, 2] = 0.25
+    t[:, 1, 3] = 0.25
+    return t
