@@ -99,6 +99,54 @@ wp_status w_transform_split(const float* x, uint16_t* xhat_hi, uint16_t* xhat_lo
 wp_status w_itransform_adj_split(const float* g, uint16_t* out_hi, uint16_t* out_lo,
                                  int64_t n1, int64_t n2, int64_t p, int L, void* stream);
 
+/* ---- Lifting with chosen predict and update operators (Sec. II-A; Remark 3.1)
+ * Level j of W_[L] = W_L ... W_1 splits the current smooth sequence of each
+ * mode-3 tube (length l = p / 2^(j-1)) into pairs; o[m] is the first and e[m]
+ * the second entry of pair m (the odd and even entries of Alg. 1, whose
+ * indices are 1-based), m = 0 .. l/2 - 1, and
+ *   d_j = o - P_j e,   s_j = e + U_j d_j,
+ *   (P_j e)[m] = sum_t predict_j[t] e[clamp(m + t - 2)], U_j likewise on d_j,
+ * indices clamped to [0, l/2 - 1] (the sequence extended by its end values).
+ * The inverse undoes the steps in reverse (e = s - U d, o = d + P e).
+ * taps: host array of L * 2 * WP_TAPS doubles, level j's predict stencil at
+ *   taps[((j-1)*2 + 0)*WP_TAPS + t], its update stencil at
+ *   taps[((j-1)*2 + 1)*WP_TAPS + t], tap t at offset t - 2; copied at the
+ *   call; every tap finite (WP_EINVAL otherwise); may be NULL when L = 0.
+ * predict = {0,0,1,0,0} and update = {0,0,0.5,0,0} at every level give the
+ * lazy transform of w_transform (same results, up to rounding order).
+ * Limit: p * 16 * element size <= 128 KiB (p <= 1024 for WP_F64, 2048 for
+ * WP_F32): a workgroup holds whole tubes in LDS.
+ */
+#define WP_TAPS 5
+#define WP_LIFT_FORWARD 0   /* W_[L]:      x -> coefficients (Eq. (1) order)    */
+#define WP_LIFT_INVERSE 1   /* W_[L]^{-1}: coefficients -> x                    */
+#define WP_LIFT_ADJ     2   /* W_[L]^T:    coefficient-space g -> spatial       */
+#define WP_LIFT_IADJ    3   /* W_[L]^{-T}: spatial g -> coefficient space       */
+
+/* One pass of the scheme (kind WP_LIFT_*) over (p, n1, n2) data; in and out
+ * must not overlap. */
+wp_status w_transform_scheme(const void* in, void* out, int64_t n1, int64_t n2, int64_t p,
+                             int L, const double* taps, int kind, int dtype, void* stream);
+
+/* WP_LIFT_FORWARD or WP_LIFT_IADJ pass of float data with the split-precision
+ * epilogue of w_transform_split (bf16 hi, and the bf16 residual lo unless
+ * out_lo is NULL). */
+wp_status w_transform_scheme_split(const float* in, uint16_t* out_hi, uint16_t* out_lo,
+                                   int64_t n1, int64_t n2, int64_t p, int L,
+                                   const double* taps, int kind, void* stream);
+
+/* w-product (Def. 2.1) under a scheme: W^{-1}( W(op A) Delta W(op B) ), all
+ * arguments as for w_product; ws must hold w_product_scheme_workspace(...)
+ * bytes.  BF16 modes split the scheme's coefficients like w_product. */
+wp_status w_product_scheme(const void* a, const void* b, void* c,
+                           int64_t n1, int64_t n2, int64_t n3, int64_t p, int L,
+                           const double* taps, int trans_a, int trans_b, int dtype, int gemm,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for w_product_scheme (0 on invalid arguments). */
+size_t w_product_scheme_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int L,
+                                  int dtype, int gemm);
+
 /* ---- Face-product (Def. 2.1, Alg. 1 middle part) ----------------------------
  * Ch[k] = op(Ah[k]) * op(Bh[k]) for k = 0..p-1, with op(X) = X or X^T per
  * slice (Def. 2.2).  op(Ah[k]) is n1 x n2, op(Bh[k]) is n2 x n3, Ch is

@@ -51,6 +51,13 @@ SIGNATURES = {
     "w_pinv": (_c_int, [_vp, _vp, _c_i64, _c_i64, _c_i64, _c_int, _c_int, ctypes.c_double, _vp,
                         _c_int, _vp, _sz, _vp]),
     "w_pinv_workspace": (_sz, [_c_i64, _c_i64, _c_i64, _c_int, _c_int, _c_int]),
+    "w_transform_scheme": (_c_int, [_vp, _vp, _c_i64, _c_i64, _c_i64, _c_int, _vp, _c_int, _c_int,
+                                    _vp]),
+    "w_transform_scheme_split": (_c_int, [_vp, _vp, _vp, _c_i64, _c_i64, _c_i64, _c_int, _vp,
+                                          _c_int, _vp]),
+    "w_product_scheme": (_c_int, [_vp, _vp, _vp, _c_i64, _c_i64, _c_i64, _c_i64, _c_int, _vp,
+                                  _c_int, _c_int, _c_int, _c_int, _vp, _sz, _vp]),
+    "w_product_scheme_workspace": (_sz, [_c_i64, _c_i64, _c_i64, _c_i64, _c_int, _c_int, _c_int]),
 }
 
 _lib = None

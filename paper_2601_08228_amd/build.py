@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libwprod.so")
-SOURCES = ["lift.hip", "gemm.hip", "svd.hip", "api.hip"]
+SOURCES = ["lift.hip", "scheme.hip", "gemm.hip", "svd.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc")
 # Packed-FP32 instructions are disabled for every HIP object.

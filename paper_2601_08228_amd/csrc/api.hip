@@ -129,6 +129,35 @@ inline ProductPlan plan_product(const FaceShapes& fs, int dtype, int gemm) {
   return pl;
 }
 
+// Host taps (L levels x {predict, update} x 5) into the kernel argument; every
+// tap finite.  L = 0 needs no taps.
+inline wp_status load_taps(const double* taps, int L, wp::SchemeTaps* out) {
+  *out = wp::SchemeTaps{};
+  if (L == 0) return WP_OK;
+  if (taps == nullptr) return WP_ENULL;
+  for (int j = 0; j < L; ++j)
+    for (int k = 0; k < 2; ++k)
+      for (int t = 0; t < WP_TAPS; ++t) {
+        const double v = taps[(j * 2 + k) * WP_TAPS + t];
+        if (!(v - v == 0.0)) return WP_EINVAL;  // NaN or infinite
+        out->w[j][k][t] = v;
+      }
+  return WP_OK;
+}
+
+inline bool scheme_fits(int64_t p, int dtype) {
+  return wp::scheme_tile_positions(p, dtype_size(dtype)) != 0;
+}
+
+inline LiftKind lift_kind(int kind) {
+  switch (kind) {
+    case WP_LIFT_INVERSE: return LiftKind::kInverse;
+    case WP_LIFT_ADJ: return LiftKind::kForwardAdj;
+    case WP_LIFT_IADJ: return LiftKind::kInverseAdj;
+    default: return LiftKind::kForward;
+  }
+}
+
 inline wp_status check_modes(int dtype, int gemm) {
   if (!valid_dtype(dtype)) return WP_EDTYPE;
   if (gemm != WP_GEMM_NATIVE && gemm != WP_GEMM_BF16 && gemm != WP_GEMM_BF16X3) return WP_EDTYPE;
@@ -288,6 +317,117 @@ wp_status w_product(const void* a, const void* b, void* c, int64_t n1, int64_t n
   return from_hip(e);
 }
 
+wp_status w_transform_scheme(const void* in, void* out, int64_t n1, int64_t n2, int64_t p, int L,
+                             const double* taps, int kind, int dtype, void* stream) {
+  if (!valid_dtype(dtype)) return WP_EDTYPE;
+  int64_t elems = 0;
+  wp_status st = check_tensor(n1, n2, p, L, &elems);
+  if (st != WP_OK) return st;
+  if (kind < WP_LIFT_FORWARD || kind > WP_LIFT_IADJ || !scheme_fits(p, dtype)) return WP_EINVAL;
+  wp::SchemeTaps tp{};
+  st = load_taps(taps, L, &tp);
+  if (st != WP_OK) return st;
+  if (in == nullptr || out == nullptr) return WP_ENULL;
+  const size_t es = dtype_size(dtype);
+  if (overlap(range_of(in, elems, es), range_of(out, elems, es))) return WP_EALIAS;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dtype == WP_F64)
+    return from_hip(wp::launch_lift_scheme_f64(lift_kind(kind), static_cast<const double*>(in),
+                                               static_cast<double*>(out), n1 * n2, p, L, tp, s));
+  return from_hip(wp::launch_lift_scheme_f32(lift_kind(kind), static_cast<const float*>(in),
+                                             static_cast<float*>(out), n1 * n2, p, L, tp, s));
+}
+
+wp_status w_transform_scheme_split(const float* in, uint16_t* out_hi, uint16_t* out_lo,
+                                   int64_t n1, int64_t n2, int64_t p, int L, const double* taps,
+                                   int kind, void* stream) {
+  int64_t elems = 0;
+  wp_status st = check_tensor(n1, n2, p, L, &elems);
+  if (st != WP_OK) return st;
+  if ((kind != WP_LIFT_FORWARD && kind != WP_LIFT_IADJ) || !scheme_fits(p, WP_F32))
+    return WP_EINVAL;
+  wp::SchemeTaps tp{};
+  st = load_taps(taps, L, &tp);
+  if (st != WP_OK) return st;
+  if (in == nullptr || out_hi == nullptr) return WP_ENULL;
+  const Range rin = range_of(in, elems, 4);
+  const Range rhi = range_of(out_hi, elems, 2);
+  const Range rlo = range_of(out_lo, elems, 2);
+  if (overlap(rin, rhi) || overlap(rin, rlo) || overlap(rhi, rlo)) return WP_EALIAS;
+  return from_hip(wp::launch_lift_scheme_f32_split(lift_kind(kind), in, out_hi, out_lo, n1 * n2,
+                                                   p, L, tp, static_cast<hipStream_t>(stream)));
+}
+
+size_t w_product_scheme_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int L,
+                                  int dtype, int gemm) {
+  if (!valid_dtype(dtype) || !scheme_fits(p, dtype)) return 0;
+  return w_product_workspace(n1, n2, n3, p, L, dtype, gemm);
+}
+
+wp_status w_product_scheme(const void* a, const void* b, void* c, int64_t n1, int64_t n2,
+                           int64_t n3, int64_t p, int L, const double* taps, int trans_a,
+                           int trans_b, int dtype, int gemm, void* ws, size_t ws_bytes,
+                           void* stream) {
+  wp_status st = check_modes(dtype, gemm);
+  if (st != WP_OK) return st;
+  FaceShapes fs{};
+  st = check_face(n1, n2, n3, p, trans_a, trans_b, &fs);
+  if (st != WP_OK) return st;
+  if (L < 0 || L > wp::kMaxLevels || p % (int64_t(1) << L) != 0) return WP_EINVAL;
+  if (!scheme_fits(p, dtype)) return WP_EINVAL;
+  wp::SchemeTaps tp{};
+  st = load_taps(taps, L, &tp);
+  if (st != WP_OK) return st;
+  if (a == nullptr || b == nullptr || c == nullptr || ws == nullptr) return WP_ENULL;
+  const ProductPlan pl = plan_product(fs, dtype, gemm);
+  if (ws_bytes < pl.total) return WP_EWORKSPACE;
+  const size_t es = dtype_size(dtype);
+  const Range ra = range_of(a, fs.a, es), rb = range_of(b, fs.b, es), rc = range_of(c, fs.c, es);
+  const Range rw{static_cast<const char*>(ws), static_cast<const char*>(ws) + ws_bytes};
+  if (overlap(rc, ra) || overlap(rc, rb) || overlap(rw, ra) || overlap(rw, rb) || overlap(rw, rc))
+    return WP_EALIAS;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = reinterpret_cast<char*>(wp::align_up(reinterpret_cast<uintptr_t>(ws), kAlign));
+  const int64_t Pa = n1 * n2, Pb = n2 * n3, Pc = n1 * n3;
+  const LiftKind F = LiftKind::kForward, I = LiftKind::kInverse;
+  hipError_t e = hipSuccess;
+  if (gemm == WP_GEMM_NATIVE) {
+    void* ah = base + pl.ah;
+    void* bh = base + pl.bh;
+    void* ch = base + pl.ch;
+    if (dtype == WP_F64) {
+      const double* A = static_cast<const double*>(a);
+      const double* B = static_cast<const double*>(b);
+      e = wp::launch_lift_scheme_f64(F, A, static_cast<double*>(ah), Pa, p, L, tp, s);
+      if (e == hipSuccess) e = wp::launch_lift_scheme_f64(F, B, static_cast<double*>(bh), Pb, p, L, tp, s);
+      if (e == hipSuccess) e = wp::launch_face_f64(static_cast<const double*>(ah), static_cast<const double*>(bh), static_cast<double*>(ch), n1, n2, n3, p, trans_a != 0, trans_b != 0, s);
+      if (e == hipSuccess) e = wp::launch_lift_scheme_f64(I, static_cast<const double*>(ch), static_cast<double*>(c), Pc, p, L, tp, s);
+    } else {
+      const float* A = static_cast<const float*>(a);
+      const float* B = static_cast<const float*>(b);
+      e = wp::launch_lift_scheme_f32(F, A, static_cast<float*>(ah), Pa, p, L, tp, s);
+      if (e == hipSuccess) e = wp::launch_lift_scheme_f32(F, B, static_cast<float*>(bh), Pb, p, L, tp, s);
+      if (e == hipSuccess) e = wp::launch_face_f32(static_cast<const float*>(ah), static_cast<const float*>(bh), static_cast<float*>(ch), n1, n2, n3, p, trans_a != 0, trans_b != 0, s);
+      if (e == hipSuccess) e = wp::launch_lift_scheme_f32(I, static_cast<const float*>(ch), static_cast<float*>(c), Pc, p, L, tp, s);
+    }
+  } else {
+    const bool x3 = gemm == WP_GEMM_BF16X3;
+    uint16_t* ahi = reinterpret_cast<uint16_t*>(base + pl.ah);
+    uint16_t* alo = x3 ? reinterpret_cast<uint16_t*>(base + pl.ah_lo) : nullptr;
+    uint16_t* bhi = reinterpret_cast<uint16_t*>(base + pl.bh);
+    uint16_t* blo = x3 ? reinterpret_cast<uint16_t*>(base + pl.bh_lo) : nullptr;
+    float* ch = reinterpret_cast<float*>(base + pl.ch);
+    e = wp::launch_lift_scheme_f32_split(F, static_cast<const float*>(a), ahi, alo, Pa, p, L, tp, s);
+    if (e == hipSuccess) e = wp::launch_lift_scheme_f32_split(F, static_cast<const float*>(b), bhi, blo, Pb, p, L, tp, s);
+    if (e == hipSuccess) e = wp::launch_face_bf16(ahi, alo, bhi, blo, ch, n1, n2, n3, p, trans_a != 0, trans_b != 0, x3, s);
+    if (e == hipSuccess) e = wp::launch_lift_scheme_f32(I, ch, static_cast<float*>(c), Pc, p, L, tp, s);
+  }
+  return from_hip(e);
+}
+
+}  // extern "C"
+
 namespace {
 
 // Shared checks of w_svd and w_svd_sparse; nsl is the number of slices the
@@ -332,6 +472,8 @@ wp_status run_svd_entry(const void* a, int64_t n1, int64_t n2, int64_t p, int L,
 }
 
 }  // namespace
+
+extern "C" {
 
 size_t w_svd_workspace(int64_t n1, int64_t n2, int64_t p, int L, int k, int dtype) {
   int64_t elems = 0, nsl = 0;

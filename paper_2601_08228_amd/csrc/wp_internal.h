@@ -32,6 +32,23 @@ hipError_t launch_lift_f32(LiftKind kind, const float* in, float* out, int64_t P
 hipError_t launch_lift_f32_split(LiftKind kind, const float* in, uint16_t* hi, uint16_t* lo,
                                  int64_t P, int64_t p, int L, hipStream_t s);
 
+// Lifting with chosen predict / update stencils (scheme.hip).  taps.w[j-1][0]
+// is the predict and taps.w[j-1][1] the update stencil of level j, tap t at
+// offset t - 2.
+struct SchemeTaps {
+  double w[kMaxLevels][2][5];
+};
+// Positions per workgroup tile for p slices of es bytes (0: p too large).
+int scheme_tile_positions(int64_t p, size_t es);
+hipError_t launch_lift_scheme_f64(LiftKind kind, const double* in, double* out, int64_t P,
+                                  int64_t p, int L, const SchemeTaps& taps, hipStream_t s);
+hipError_t launch_lift_scheme_f32(LiftKind kind, const float* in, float* out, int64_t P,
+                                  int64_t p, int L, const SchemeTaps& taps, hipStream_t s);
+// Forward or W^{-T} pass of float data written as bf16 hi (+ optional lo) planes.
+hipError_t launch_lift_scheme_f32_split(LiftKind kind, const float* in, uint16_t* hi,
+                                        uint16_t* lo, int64_t P, int64_t p, int L,
+                                        const SchemeTaps& taps, hipStream_t s);
+
 // Face-product GEMMs.  C[k] = op(A[k]) op(B[k]), op(A) m x kk, op(B) kk x n.
 hipError_t launch_face_f64(const double* a, const double* b, double* c, int64_t m, int64_t kk,
                            int64_t n, int64_t batch, bool ta, bool tb, hipStream_t s);

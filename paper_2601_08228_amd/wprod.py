@@ -11,6 +11,7 @@ the hi / lo parts.
 import collections
 import ctypes
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -20,7 +21,8 @@ __all__ = [
     "w_transform_split", "w_itransform_adj_split", "w_face_product",
     "w_face_product_split", "w_product", "w_product_workspace", "w_svd",
     "w_svd_workspace", "w_svd_sparse", "w_svd_sparse_workspace", "SvdResult", "w_pinv",
-    "w_pinv_workspace",
+    "w_pinv_workspace", "SCHEME_KINDS", "w_transform_scheme", "w_transform_scheme_split",
+    "w_product_scheme", "w_product_scheme_workspace",
 ]
 
 _DT = {torch.float64: _lib.WP_F64, torch.float32: _lib.WP_F32}
@@ -271,3 +273,78 @@ def w_pinv(a, L, sparse=False, rtol=0.0, workspace=None):
                         workspace.numel() * workspace.element_size(), _stream(a))
     _lib.check("w_pinv", st)
     return out, info
+
+
+# ---- lifting with chosen predict / update stencils (Sec. II-A; Remark 3.1) ----
+
+SCHEME_KINDS = {"forward": 0, "inverse": 1, "adj": 2, "iadj": 3}
+
+
+def _taps(taps, L):
+    """Host copy of the taps as a C-contiguous float64 array of shape (L, 2, 5)."""
+    t = np.ascontiguousarray(np.asarray(taps, dtype=np.float64))
+    if t.shape != (int(L), 2, 5):
+        raise ValueError("taps must have shape (%d, 2, 5), got %s" % (int(L), t.shape))
+    return t
+
+
+def w_transform_scheme(x, L, taps, kind="forward", out=None):
+    """One pass of the lifting with stencils taps (L, 2, 5): kind 'forward' (W),
+    'inverse' (W^{-1}), 'adj' (W^T) or 'iadj' (W^{-T})."""
+    _dev_tensor(x, "x", tuple(_DT))
+    t = _taps(taps, L)
+    if out is None:
+        out = torch.empty_like(x)
+    else:
+        _dev_tensor(out, "out", (x.dtype,))
+        if out.shape != x.shape:
+            raise ValueError("out has the wrong shape")
+    p, n1, n2 = x.shape
+    with torch.cuda.device(x.device):
+        st = _lib.load().w_transform_scheme(_ptr(x), _ptr(out), n1, n2, p, int(L),
+                                            t.ctypes.data, SCHEME_KINDS[kind], _DT[x.dtype],
+                                            _stream(x))
+    _lib.check("w_transform_scheme", st)
+    return out
+
+
+def w_transform_scheme_split(x, L, taps, kind="forward", with_lo=True):
+    """'forward' or 'iadj' pass of float32 x with bf16 hi / lo outputs."""
+    _dev_tensor(x, "x", (torch.float32,))
+    t = _taps(taps, L)
+    hi = torch.empty(x.shape, dtype=torch.bfloat16, device=x.device)
+    lo = torch.empty(x.shape, dtype=torch.bfloat16, device=x.device) if with_lo else None
+    p, n1, n2 = x.shape
+    with torch.cuda.device(x.device):
+        st = _lib.load().w_transform_scheme_split(_ptr(x), _ptr(hi), _ptr(lo), n1, n2, p, int(L),
+                                                  t.ctypes.data, SCHEME_KINDS[kind], _stream(x))
+    _lib.check("w_transform_scheme_split", st)
+    return hi, lo
+
+
+def w_product_scheme_workspace(n1, n2, n3, p, L, dtype=torch.float32, gemm="native"):
+    return int(_lib.load().w_product_scheme_workspace(n1, n2, n3, p, int(L), _DT[dtype],
+                                                      _lib.GEMM_MODES[gemm]))
+
+
+def w_product_scheme(a, b, L, taps, trans_a=False, trans_b=False, gemm="native", out=None,
+                     workspace=None):
+    """w-product (Def. 2.1) under the lifting with stencils taps (L, 2, 5)."""
+    _dev_tensor(a, "a", tuple(_DT))
+    _dev_tensor(b, "b", (a.dtype,))
+    t = _taps(taps, L)
+    p, n1, n2, n3 = _face_dims(a, b, trans_a, trans_b)
+    mode = _lib.GEMM_MODES[gemm]
+    need = w_product_scheme_workspace(n1, n2, n3, p, L, a.dtype, gemm)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=a.device)
+    if out is None:
+        out = torch.empty((p, n1, n3), dtype=a.dtype, device=a.device)
+    with torch.cuda.device(a.device):
+        st = _lib.load().w_product_scheme(_ptr(a), _ptr(b), _ptr(out), n1, n2, n3, p, int(L),
+                                          t.ctypes.data, int(trans_a), int(trans_b),
+                                          _DT[a.dtype], mode, _ptr(workspace),
+                                          workspace.numel() * workspace.element_size(),
+                                          _stream(a))
+    _lib.check("w_product_scheme", st)
+    return out

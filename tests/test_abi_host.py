@@ -32,7 +32,8 @@ def test_header_declares_expected_entry_points():
                  "w_transform_split", "w_itransform_adj_split", "w_face_product",
                  "w_face_product_split", "w_product", "w_product_workspace", "w_svd",
                  "w_svd_workspace", "w_svd_sparse", "w_svd_sparse_workspace", "w_pinv",
-                 "w_pinv_workspace", "w_status_string", "w_version"]:
+                 "w_pinv_workspace", "w_transform_scheme", "w_transform_scheme_split",
+                 "w_product_scheme", "w_product_scheme_workspace", "w_status_string", "w_version"]:
         assert must in names, must
 
 
@@ -185,6 +186,63 @@ def test_pinv_validation(lib):
     # info (16 int32) overlapping the output.
     assert f(A, OUT, 8, 6, 16, 2, 0, 0.0, ctypes.c_void_p(0x500000 + 3068), 1, W, need,
              NULL) == -3
+
+
+def _taps(L, fill=0.25):
+    import numpy as np
+    return np.full((L, 2, 5), fill)
+
+
+def test_scheme_transform_validation(lib):
+    import numpy as np
+    f = lib.w_transform_scheme
+    t = _taps(2)
+    T = t.ctypes.data
+    assert f(A, B, 4, 4, 12, 3, T, 0, 1, NULL) == -1               # p not divisible by 2^L
+    assert f(A, B, 4, 4, 16, 2, T, 4, 1, NULL) == -1               # unknown kind
+    assert f(A, B, 4, 4, 16, 2, T, 0, 2, NULL) == -4               # bad dtype
+    assert f(A, B, 4, 4, 16, 2, None, 0, 1, NULL) == -2            # taps missing
+    bad = _taps(2)
+    bad[1, 1, 3] = np.nan
+    assert f(A, B, 4, 4, 16, 2, bad.ctypes.data, 0, 1, NULL) == -1
+    bad[1, 1, 3] = np.inf
+    assert f(A, B, 4, 4, 16, 2, bad.ctypes.data, 0, 1, NULL) == -1
+    assert f(A, B, 4, 4, 2048, 2, T, 0, 0, NULL) == -1             # FP64 tubes too long for LDS
+    assert f(NULL, B, 4, 4, 16, 2, T, 0, 1, NULL) == -2
+    # a holds 4 * 4 * 16 floats = 1024 bytes: an output starting inside it aliases.
+    assert f(A, ctypes.c_void_p(0x100000 + 1020), 4, 4, 16, 2, T, 0, 1, NULL) == -3
+    g = lib.w_transform_scheme_split
+    assert g(A, B, C, 4, 4, 16, 2, T, 1, NULL) == -1               # split only for W and W^{-T}
+    assert g(A, B, C, 4, 4, 16, 2, None, 0, NULL) == -2
+    assert g(A, ctypes.c_void_p(0x100000 + 1000), C, 4, 4, 16, 2, T, 0, NULL) == -3
+
+
+def test_scheme_product_validation(lib):
+    import numpy as np
+    t = _taps(2)
+    assert lib.w_product_scheme_workspace(3, 4, 5, 16, 2, 1, 0) == \
+        lib.w_product_workspace(3, 4, 5, 16, 2, 1, 0)
+    assert lib.w_product_scheme_workspace(3, 4, 5, 4096, 2, 1, 0) == 0   # p too long
+    need = lib.w_product_scheme_workspace(3, 4, 5, 16, 2, 1, 2)
+    assert need > 0
+    f = lib.w_product_scheme
+    assert f(A, B, C, 3, 4, 5, 16, 2, t.ctypes.data, 0, 0, 1, 2, WS, need - 1, NULL) == -5
+    assert f(A, B, C, 3, 4, 5, 16, 2, t.ctypes.data, 0, 0, 0, 2, WS, need, NULL) == -4
+    assert f(A, B, C, 3, 4, 5, 16, 2, None, 0, 0, 1, 2, WS, need, NULL) == -2
+    bad = _taps(2)
+    bad[0, 0, 0] = np.nan
+    assert f(A, B, C, 3, 4, 5, 16, 2, bad.ctypes.data, 0, 0, 1, 2, WS, need, NULL) == -1
+    assert f(A, B, C, 3, 4, 5, 16, 2, t.ctypes.data, 2, 0, 1, 2, WS, need, NULL) == -1
+
+
+def test_named_schemes_match_the_oracle():
+    import numpy as np
+    import oracle as orc
+    from paper_2601_08228_amd import schemes
+    for L in (1, 3):
+        np.testing.assert_array_equal(schemes.lazy(L), orc.lazy_scheme(L))
+        np.testing.assert_array_equal(schemes.interpolating(L), orc.interpolating_scheme(L))
+        np.testing.assert_array_equal(schemes.cdf53(L), orc.cdf53_scheme(L))
 
 
 def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
