@@ -16,11 +16,12 @@ outside the timed steps.  Prints one JSON line.
 
 With --sp-w-svd it instead compares w-svd and sp-w-svd (Sec. IV-B) on a
 256x192x96 hyperspectral-like cube at L = 5; --pinv-deblur times the
-pseudo-inverse deblurring of Sec. IV-C; --table1 the p x p x p w-products of
-Table 1; --configs the other workloads.  Each prints its own JSON line.
+pseudo-inverse deblurring of Sec. IV-C; --schemes the lifting with chosen
+predict / update stencils; --table1 the p x p x p w-products of Table 1;
+--configs the other workloads.  Each prints its own JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--sp-w-svd | --pinv-deblur | --table1 | --configs]
+                       [--sp-w-svd | --pinv-deblur | --schemes | --table1 | --configs]
 """
 
 import argparse
@@ -62,6 +63,10 @@ def parse():
     ap.add_argument("--pinv-deblur", action="store_true",
                     help="instead of the step: pseudo-inverse deblurring (Sec. IV-C) of "
                          "PaviaU-, Salinas- and Botswana-shaped hyperspectral-like cubes, FP64")
+    ap.add_argument("--schemes", action="store_true",
+                    help="instead of the step: lifting with chosen predict / update stencils "
+                         "(lazy, interpolating, CDF 5/3) on 512x512x256 FP32, passes and "
+                         "bf16x3 w-product")
     ap.add_argument("--configs", action="store_true",
                     help="instead of the step: the other workloads (FP64 small case, config-3 "
                          "PSNR, 1024x1024x128 precision modes, 50-step deblurring solve)")
@@ -134,6 +139,9 @@ def main():
         return
     if args.pinv_deblur:
         deblur_report(torch, wp, synth, dev, args)
+        return
+    if args.schemes:
+        schemes_report(torch, wp, synth, dev, args)
         return
 
     a = synth.normal_device((P, N1, N2), 21, dev)
@@ -495,6 +503,107 @@ def deblur_report(torch, wp, synth, dev, args):
             "value": cpu["ms"], "unit": "ms", "cores": host_threads(), "kind": "oracle",
             "sample": "FP64 NumPy oracle of the PaviaU sparse deblurring, whole cube, one call",
             "rel_err_gpu_vs_oracle": cpu["rel_err_gpu_vs_oracle"]}
+    print(json.dumps(line), flush=True)
+
+
+def schemes_report(torch, wp, synth, dev, args):
+    """Lifting with chosen predict / update stencils (Sec. II-A; Remark 3.1).
+
+    On the w-product operands of the step (512x512x256 FP32 N(0,1), L = 4):
+    each pass of the lazy, interpolating (Example 2.1) and CDF 5/3 stencils
+    against the lazy kernels, as ms and HBM GB/s (read once, written once),
+    and the bf16x3 w-product under each scheme.  Passes are checked against
+    the FP64 oracle on 2048 sampled tubes; the oracle's forward pass is timed
+    on the host on a 256x256x256 sample.
+    """
+    import oracle
+    from paper_2601_08228_amd import schemes as sch
+    reps = max(args.steps, 1)
+    x = synth.normal_device((P, N1, N2), 21, dev)
+    y = synth.normal_device((P, N2, N3), 22, dev)
+    nbytes = 2 * x.numel() * 4
+
+    def ev_ms(fn):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    named = {"lazy": sch.lazy(LEV), "interpolating": sch.interpolating(LEV),
+             "cdf53": sch.cdf53(LEV)}
+    rng = np.random.default_rng(5)
+    cols = rng.choice(N1 * N2, size=2048, replace=False)
+    xs = x.reshape(P, -1)[:, torch.as_tensor(cols, device=dev)].double().cpu().numpy()
+    rows = {}
+    lazy_kernels = {"forward": wp.w_transform, "inverse": wp.w_itransform,
+                    "adj": wp.w_transform_adj, "iadj": wp.w_itransform_adj}
+    rows["lazy_kernels"] = {k: {"ms": round(ev_ms(lambda: f(x, LEV)), 4)}
+                            for k, f in lazy_kernels.items()}
+    for k in rows["lazy_kernels"].values():
+        k["GBps"] = round(nbytes / k["ms"] / 1e6, 1)
+    fwd_ms = {}
+    for name, taps in named.items():
+        r = {}
+        for kind in ("forward", "inverse", "adj", "iadj"):
+            ms = ev_ms(lambda: wp.w_transform_scheme(x, LEV, taps, kind))
+            out = wp.w_transform_scheme(x, LEV, taps, kind)
+            got = out.reshape(P, -1)[:, torch.as_tensor(cols, device=dev)].double().cpu().numpy()
+            ref = {"forward": oracle.lift_fwd_scheme, "inverse": oracle.lift_inv_scheme,
+                   "adj": oracle.lift_fwd_scheme_adj,
+                   "iadj": oracle.lift_inv_scheme_adj}[kind](xs, LEV, taps)
+            err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            r[kind] = {"ms": round(ms, 4), "GBps": round(nbytes / ms / 1e6, 1),
+                       "hbm_frac": round(nbytes / ms / 1e6 / HBM_PEAK_GBS, 3),
+                       "rel_err_sampled_tubes": err}
+            if kind == "forward":
+                fwd_ms[name] = ms
+        pm = ev_ms(lambda: wp.w_product_scheme(x, y, LEV, taps, gemm="bf16x3"))
+        r["w_product_bf16x3_ms"] = round(pm, 4)
+        r["w_product_bf16x3_TFLOPs"] = round(2.0 * N1 * N2 * N3 * P / pm / 1e9, 1)
+        rows[name] = r
+    lazy_prod = ev_ms(lambda: wp.w_product(x, y, LEV, gemm="bf16x3"))
+    rows["lazy_kernels"]["w_product_bf16x3_ms"] = round(lazy_prod, 4)
+    # Host oracle on a sample (forward CDF 5/3 pass).
+    sample = synth.normal((P, 256, 256), 23)
+    t0 = time.perf_counter()
+    oracle.lift_fwd_scheme(sample, LEV, named["cdf53"])
+    cpu_s = time.perf_counter() - t0
+    cpu_gbps = 2 * sample.size * 4 / cpu_s / 1e9
+    ms = fwd_ms["cdf53"]
+    line = {
+        "metric": "lifting-scheme pass HBM throughput (CDF 5/3 forward, FP32, 512x512x256, L=4)",
+        "value": round(nbytes / ms / 1e6, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": reps,
+        "warmup": args.warmup,
+        "higher_is_better": True,
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "lifting passes with chosen predict / update stencils (lazy, "
+                               "interpolating, CDF 5/3) on a 512x512x256 N(0,1) FP32 tensor, "
+                               "L=4, and the bf16x3 w-product 512x512x512 per slice x 256 under "
+                               "each scheme; value: CDF 5/3 forward pass",
+                   "p": P, "n1": N1, "n2": N2, "L": LEV},
+        "roofline": {"bound": "hbm", "achieved": round(nbytes / ms / 1e6, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(nbytes / ms / 1e6 / HBM_PEAK_GBS, 3), "traffic": None,
+                     "kernel": "lift_scheme_kernel<float, kForward>",
+                     "algorithmic_bytes": nbytes},
+        "schemes": rows,
+        "cpu_baseline": {"value": round(cpu_gbps, 3), "unit": "GB/s", "cores": host_threads(),
+                         "kind": "oracle",
+                         "sample": "FP64 NumPy oracle CDF 5/3 forward pass on a 256x256x256 "
+                                   "tensor (FP32-equivalent bytes, %.2f s)" % cpu_s},
+    }
     print(json.dumps(line), flush=True)
 
 

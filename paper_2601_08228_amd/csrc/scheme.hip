@@ -42,25 +42,31 @@ __device__ __forceinline__ int coeff_row(int c, int p, int L) {
 
 __device__ __forceinline__ int clampi(int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); }
 
-// sum_t w[t] g[clamp(m + t - 2)] over rows g(k) = buf[(base + k * stride) * TP + q].
-template <typename T>
-__device__ __forceinline__ T stencil(const T* buf, const double* w, int m, int n, int base,
-                                     int stride, int tp, int q) {
-  T acc = T(0);
+// V consecutive positions as one vector (16-byte loads and LDS accesses when
+// V * sizeof(T) = 16).
+template <typename T, int V>
+using Vec = T __attribute__((ext_vector_type(V)));
+
+// sum_t w[t] g[clamp(m + t - 2)] over rows g(k) = buf[base + k * stride] (a
+// row is TP / V vectors wide; `col` selects this thread's vector).
+template <typename T, int V>
+__device__ __forceinline__ Vec<T, V> stencil(const Vec<T, V>* buf, const double* w, int m, int n,
+                                             int base, int stride, int rowv, int col) {
+  Vec<T, V> acc = T(0);
 #pragma unroll
   for (int t = 0; t < 5; ++t) {
     if (w[t] == 0.0) continue;
     const int k = clampi(m + t - 2, n - 1);
-    acc = fma(T(w[t]), buf[(base + k * stride) * tp + q], acc);
+    acc += T(w[t]) * buf[(base + k * stride) * rowv + col];
   }
   return acc;
 }
 
 // Transposed stencil: sum over m, t with clamp(m + t - 2) = i of w[t] g(m).
-template <typename T>
-__device__ __forceinline__ T stencil_t(const T* buf, const double* w, int i, int n, int base,
-                                       int stride, int tp, int q) {
-  T acc = T(0);
+template <typename T, int V>
+__device__ __forceinline__ Vec<T, V> stencil_t(const Vec<T, V>* buf, const double* w, int i,
+                                               int n, int base, int stride, int rowv, int col) {
+  Vec<T, V> acc = T(0);
 #pragma unroll
   for (int t = 0; t < 5; ++t) {
     if (w[t] == 0.0) continue;
@@ -79,27 +85,42 @@ __device__ __forceinline__ T stencil_t(const T* buf, const double* w, int i, int
       lo = hi = i - off;
       if (lo < 0 || lo > n - 1) continue;
     }
-    for (int m = lo; m <= hi; ++m) acc = fma(T(w[t]), buf[(base + m * stride) * tp + q], acc);
+    for (int m = lo; m <= hi; ++m) acc += T(w[t]) * buf[(base + m * stride) * rowv + col];
   }
   return acc;
 }
 
-template <typename T, LiftKind K, bool SPLIT>
+// Rows per batch of global loads (kept in registers before the LDS stores,
+// so that a thread has that many loads in flight).
+constexpr int kBatch = 8;
+
+template <typename T, int V, LiftKind K, bool SPLIT>
 __global__ __launch_bounds__(kSchemeThreads) void lift_scheme_kernel(
     const T* __restrict__ in, T* __restrict__ out, uint16_t* __restrict__ hi,
     uint16_t* __restrict__ lo, int64_t P, int p, int L, int tp, SchemeTaps taps) {
+  using VT = Vec<T, V>;
   extern __shared__ unsigned char s_raw[];
-  T* buf = reinterpret_cast<T*>(s_raw);
-  const int q = threadIdx.x % tp;
-  const int r0 = threadIdx.x / tp;
-  const int rstep = kSchemeThreads / tp;
-  const int64_t pos = int64_t(blockIdx.x) * tp + q;
-  const bool live = pos < P;
+  VT* buf = reinterpret_cast<VT*>(s_raw);
+  const int rowv = tp / V;                   // vectors per row
+  const int col = threadIdx.x % rowv;
+  const int r0 = threadIdx.x / rowv;
+  const int rstep = kSchemeThreads / rowv;
+  const int64_t pos = int64_t(blockIdx.x) * tp + int64_t(col) * V;
+  const bool live = pos < P;                 // P is a multiple of V
   constexpr bool kCoeffIn = K == LiftKind::kInverse || K == LiftKind::kForwardAdj;
 
-  for (int c = r0; c < p; c += rstep) {
-    const int row = kCoeffIn ? coeff_row(c, p, L) : c;
-    buf[row * tp + q] = live ? in[int64_t(c) * P + pos] : T(0);
+  for (int c0 = r0; c0 < p; c0 += rstep * kBatch) {
+    VT v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int c = c0 + u * rstep;
+      v[u] = (live && c < p) ? *reinterpret_cast<const VT*>(in + int64_t(c) * P + pos) : VT(T(0));
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int c = c0 + u * rstep;
+      if (c < p) buf[(kCoeffIn ? coeff_row(c, p, L) : c) * rowv + col] = v[u];
+    }
   }
   __syncthreads();
 
@@ -111,16 +132,16 @@ __global__ __launch_bounds__(kSchemeThreads) void lift_scheme_kernel(
       const double* uw = taps.w[j - 1][1];
       if constexpr (K == LiftKind::kForward) {
         for (int m = r0; m < n; m += rstep)  // d = o - P e
-          buf[(ob + m * st) * tp + q] -= stencil(buf, pw, m, n, eb, st, tp, q);
+          buf[(ob + m * st) * rowv + col] -= stencil<T, V>(buf, pw, m, n, eb, st, rowv, col);
         __syncthreads();
         for (int m = r0; m < n; m += rstep)  // s = e + U d
-          buf[(eb + m * st) * tp + q] += stencil(buf, uw, m, n, ob, st, tp, q);
+          buf[(eb + m * st) * rowv + col] += stencil<T, V>(buf, uw, m, n, ob, st, rowv, col);
       } else {
         for (int i = r0; i < n; i += rstep)  // g_s = g_e + P^T g_o
-          buf[(eb + i * st) * tp + q] += stencil_t(buf, pw, i, n, ob, st, tp, q);
+          buf[(eb + i * st) * rowv + col] += stencil_t<T, V>(buf, pw, i, n, ob, st, rowv, col);
         __syncthreads();
         for (int i = r0; i < n; i += rstep)  // g_d = g_o - U^T g_s
-          buf[(ob + i * st) * tp + q] -= stencil_t(buf, uw, i, n, eb, st, tp, q);
+          buf[(ob + i * st) * rowv + col] -= stencil_t<T, V>(buf, uw, i, n, eb, st, rowv, col);
       }
       __syncthreads();
     }
@@ -132,16 +153,16 @@ __global__ __launch_bounds__(kSchemeThreads) void lift_scheme_kernel(
       const double* uw = taps.w[j - 1][1];
       if constexpr (K == LiftKind::kInverse) {
         for (int m = r0; m < n; m += rstep)  // e = s - U d
-          buf[(eb + m * st) * tp + q] -= stencil(buf, uw, m, n, ob, st, tp, q);
+          buf[(eb + m * st) * rowv + col] -= stencil<T, V>(buf, uw, m, n, ob, st, rowv, col);
         __syncthreads();
         for (int m = r0; m < n; m += rstep)  // o = d + P e
-          buf[(ob + m * st) * tp + q] += stencil(buf, pw, m, n, eb, st, tp, q);
+          buf[(ob + m * st) * rowv + col] += stencil<T, V>(buf, pw, m, n, eb, st, rowv, col);
       } else {
         for (int i = r0; i < n; i += rstep)  // g_o = g_d + U^T g_s
-          buf[(ob + i * st) * tp + q] += stencil_t(buf, uw, i, n, eb, st, tp, q);
+          buf[(ob + i * st) * rowv + col] += stencil_t<T, V>(buf, uw, i, n, eb, st, rowv, col);
         __syncthreads();
         for (int i = r0; i < n; i += rstep)  // g_e = g_s - P^T g_o
-          buf[(eb + i * st) * tp + q] -= stencil_t(buf, pw, i, n, ob, st, tp, q);
+          buf[(eb + i * st) * rowv + col] -= stencil_t<T, V>(buf, pw, i, n, ob, st, rowv, col);
       }
       __syncthreads();
     }
@@ -149,31 +170,35 @@ __global__ __launch_bounds__(kSchemeThreads) void lift_scheme_kernel(
 
   if (!live) return;
   for (int c = r0; c < p; c += rstep) {
-    const int row = kCoeffIn ? c : coeff_row(c, p, L);
-    const T v = buf[row * tp + q];
+    const VT v = buf[(kCoeffIn ? c : coeff_row(c, p, L)) * rowv + col];
     if constexpr (SPLIT) {
       // bf16 hi and the bf16 residual, both rounded to nearest even; x - hi is
       // exact in FP32.
-      const __bf16 hb = static_cast<__bf16>(v);
-      hi[int64_t(c) * P + pos] = __builtin_bit_cast(uint16_t, hb);
-      if (lo != nullptr) {
-        const __bf16 lb = static_cast<__bf16>(float(v) - static_cast<float>(hb));
-        lo[int64_t(c) * P + pos] = __builtin_bit_cast(uint16_t, lb);
+      using HV = Vec<uint16_t, V>;
+      HV h, l;
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        const __bf16 hb = static_cast<__bf16>(v[i]);
+        h[i] = __builtin_bit_cast(uint16_t, hb);
+        l[i] = __builtin_bit_cast(uint16_t,
+                                  static_cast<__bf16>(float(v[i]) - static_cast<float>(hb)));
       }
+      *reinterpret_cast<HV*>(hi + int64_t(c) * P + pos) = h;
+      if (lo != nullptr) *reinterpret_cast<HV*>(lo + int64_t(c) * P + pos) = l;
     } else {
-      out[int64_t(c) * P + pos] = v;
+      *reinterpret_cast<VT*>(out + int64_t(c) * P + pos) = v;
     }
   }
 }
 
-template <typename T, LiftKind K, bool SPLIT>
-hipError_t launch_one(const T* in, T* out, uint16_t* hi, uint16_t* lo, int64_t P, int64_t p,
-                      int L, const SchemeTaps& taps, hipStream_t s) {
+template <typename T, int V, LiftKind K, bool SPLIT>
+hipError_t launch_v(const T* in, T* out, uint16_t* hi, uint16_t* lo, int64_t P, int64_t p,
+                    int L, const SchemeTaps& taps, hipStream_t s) {
   int tp = scheme_tile_positions(p, sizeof(T));
   if (tp == 0) return hipErrorInvalidValue;
-  while (tp > 1 && int64_t(tp / 2) >= P) tp /= 2;  // no wider than the tensor
+  while (tp > V && int64_t(tp / 2) >= P) tp /= 2;  // no wider than the tensor
   const size_t lds = size_t(p) * tp * sizeof(T);
-  auto kern = lift_scheme_kernel<T, K, SPLIT>;
+  auto kern = lift_scheme_kernel<T, V, K, SPLIT>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   if (e != hipSuccess) return e;
@@ -183,6 +208,19 @@ hipError_t launch_one(const T* in, T* out, uint16_t* hi, uint16_t* lo, int64_t P
   return hipGetLastError();
 }
 
+inline bool aligned16(const void* x) { return (reinterpret_cast<uintptr_t>(x) & 15) == 0; }
+
+// 16-byte vectors when every row of the tensor starts on a 16-byte boundary.
+template <typename T, LiftKind K, bool SPLIT>
+hipError_t launch_one(const T* in, T* out, uint16_t* hi, uint16_t* lo, int64_t P, int64_t p,
+                      int L, const SchemeTaps& taps, hipStream_t s) {
+  constexpr int V = 16 / sizeof(T);
+  const bool vec = P % V == 0 && aligned16(in) && (SPLIT ? (P % 8 == 0 && aligned16(hi) &&
+                                                            (lo == nullptr || aligned16(lo)))
+                                                         : aligned16(out));
+  if (vec) return launch_v<T, V, K, SPLIT>(in, out, hi, lo, P, p, L, taps, s);
+  return launch_v<T, 1, K, SPLIT>(in, out, hi, lo, P, p, L, taps, s);
+}
 template <typename T>
 hipError_t dispatch(LiftKind kind, const T* in, T* out, int64_t P, int64_t p, int L,
                     const SchemeTaps& taps, hipStream_t s) {
@@ -204,10 +242,10 @@ hipError_t dispatch(LiftKind kind, const T* in, T* out, int64_t P, int64_t p, in
 }  // namespace
 
 int scheme_tile_positions(int64_t p, size_t es) {
-  // Widest power-of-two tile (up to 256 positions) within 64 KiB of LDS, at
+  // Widest power-of-two tile (up to 256 positions) within 32 KiB of LDS, at
   // least 16 positions; 0 if 16 positions would need more than 128 KiB.
   int tp = 256;
-  while (tp > 16 && size_t(p) * tp * es > 65536) tp /= 2;
+  while (tp > 16 && size_t(p) * tp * es > 32768) tp /= 2;
   return size_t(p) * tp * es <= 131072 ? tp : 0;
 }
 
