@@ -987,17 +987,25 @@ __global__ __launch_bounds__(256) void max_reduce_kernel(const double* __restric
   if (threadIdx.x == 0) *out = red[0];
 }
 
-// Which Jacobi kernel a slice shape takes.  Register-resident kernel when the
-// columns fit: each of up to 32 units (16-lane rows) owns J slots, J the
-// smallest power of two with 32 * J >= nc_pad / 2, rpl rows per lane; the
-// block kernel otherwise.
+// Which Jacobi kernel a call takes.  Register-resident kernel when the
+// columns fit (each of up to 32 units of 16 lanes owns J slots, J the
+// smallest power of two with 32 * J >= nc_pad / 2, rpl rows per lane) and
+// there are enough slices to occupy the chip with one workgroup each (64 or
+// more, or narrow slices); the block kernel, which spreads a slice over
+// several workgroups, otherwise.
+// Slice count from which one workgroup per slice beats the block kernel
+// (measured: 6 slices of 256 x 192 run 1.8x faster in the block kernel, 96
+// take the same time both ways, 192 of 256 x 256 run 1.4x faster in the
+// register kernel).
+constexpr int64_t kRegMinSlices = 64;
+
 struct JacobiChoice {
   bool reg;
   int J, nunits, rpl;
   BjShape bj;
 };
 
-inline JacobiChoice choose_jacobi(int mr, int nc, size_t es) {
+inline JacobiChoice choose_jacobi(int mr, int nc, size_t es, int64_t nsl) {
   JacobiChoice c{};
   int ncp = nc + (nc & 1);
   if (ncp < 2) ncp = 2;
@@ -1007,7 +1015,8 @@ inline JacobiChoice choose_jacobi(int mr, int nc, size_t es) {
   c.nunits = (half + c.J - 1) / c.J;
   c.rpl = 1;
   while (c.rpl * 16 < mr) c.rpl *= 2;
-  c.reg = c.rpl <= 16 && c.J <= 4 && (es == 4 || (c.rpl <= 8 && c.J * c.rpl <= 16));
+  c.reg = c.rpl <= 16 && c.J <= 4 && (es == 4 || (c.rpl <= 8 && c.J * c.rpl <= 16)) &&
+          (nsl >= kRegMinSlices || nc < 32);
   c.bj = bj_shape(mr, nc);
   return c;
 }
@@ -1021,7 +1030,7 @@ struct SvdPlan {
 inline SvdPlan plan_svd(int64_t n1, int64_t n2, int64_t p, int64_t nsl, int k, size_t es) {
   const int64_t mr = n1 > n2 ? n1 : n2;
   const int64_t nc = n1 > n2 ? n2 : n1;
-  const JacobiChoice jc = choose_jacobi(int(mr), int(nc), es);
+  const JacobiChoice jc = choose_jacobi(int(mr), int(nc), es, nsl);
   const int64_t ncw = jc.reg ? nc : int64_t(jc.bj.nbp) * jc.bj.B;  // columns of W
   SvdPlan pl{};
   size_t off = 0;
@@ -1082,7 +1091,7 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
   d.trans = n1 < n2 ? 1 : 0;
   if (max_sweeps <= 0) max_sweeps = sizeof(T) == 8 ? 30 : 20;
 
-  const JacobiChoice jc = choose_jacobi(d.mr, d.nc, sizeof(T));
+  const JacobiChoice jc = choose_jacobi(d.mr, d.nc, sizeof(T), nsl);
   if (jc.reg) {
     const dim3 grid{unsigned(nsl)};
     const dim3 block{unsigned(kJacobiThreads)};
