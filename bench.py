@@ -356,6 +356,9 @@ def sparse_report(torch, wp, synth, dev, args):
             "rel_err_vs_oracle": {"w_svd_Ak": rel(ak_f, ak_full), "sp_w_svd_Ak": rel(ak_s, ak_sp)},
         }
         cpu_ms[str(rk)] = {"w_svd": round((t1 - t0) * 1e3, 1), "sp_w_svd": round((t2 - t1) * 1e3, 1)}
+    _, rs32 = time_call(lambda: wp.w_svd_sparse(x, T3_L, 32))
+    sp_flops = jacobi_flops(rs32.info.cpu().numpy(), T3_N1, T3_N2)
+    sp_ms = rows["32"]["sp_w_svd_ms"]
     line = {
         "metric": "sp-w-svd and w-svd time (FP32, 256x192x96 hyperspectral-like, L=5)",
         "value": rows["32"]["sp_w_svd_ms"],
@@ -371,6 +374,13 @@ def sparse_report(torch, wp, synth, dev, args):
                                "(12 components, noise 0.01), L=5, ranks 2/8/32/64; value at rank 32",
                    "n1": T3_N1, "n2": T3_N2, "p": T3_P, "L": T3_L},
         "ranks": rows,
+        "roofline": {"bound": "alu", "achieved": round(sp_flops / sp_ms / 1e9, 2),
+                     "peak": FP32_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": round(sp_flops / sp_ms / 1e9 / FP32_PEAK_TFS, 4), "traffic": None,
+                     "kernel": "bj_round_kernel<float, 16, 8> (block Jacobi, 6 slices)",
+                     "algorithmic_flops_per_call": sp_flops,
+                     "note": "12*mr flops per pair visit times the sweeps of each slice; "
+                             "duration = whole sp-w-svd call at rank 32"},
         "cpu_baseline": {
             "value": cpu_ms["32"]["sp_w_svd"], "unit": "ms", "cores": host_threads(),
             "kind": "oracle",
@@ -457,8 +467,11 @@ def deblur_report(torch, wp, synth, dev, args):
             for c in (0, (p >> L) // 2, (p >> L) - 1):
                 want = np.linalg.solve(tv, np.linalg.solve(th, bhat[c].T).T)
                 errs.append(rel(xhat[c], want))
+            jf = jacobi_flops(iv.cpu().numpy(), n1, n1) + jacobi_flops(ih.cpu().numpy(), n2, n2)
             row[key] = {
                 "ms": round(ms, 3),
+                "jacobi_flops": jf,
+                "jacobi_TFLOPs_over_call": round(jf / ms / 1e9, 3),
                 "pinv_av_ms": round(ev[0].elapsed_time(ev[1]), 3),
                 "pinv_ah_ms": round(ev[1].elapsed_time(ev[2]), 3),
                 "w_products_ms": round(ev[2].elapsed_time(ev[4]), 3),
@@ -498,6 +511,14 @@ def deblur_report(torch, wp, synth, dev, args):
                    "blur_b": DEBLUR_B},
         "cases": cases,
     }
+    sal = cases["Salinas"]["sp_w_product"]
+    line["roofline"] = {
+        "bound": "alu", "achieved": sal["jacobi_TFLOPs_over_call"], "peak": FP64_VALU_PEAK_TFS,
+        "unit": "TFLOP/s", "frac": round(sal["jacobi_TFLOPs_over_call"] / FP64_VALU_PEAK_TFS, 4),
+        "traffic": None, "kernel": "bj_round_kernel<double, 16, 16> (block Jacobi)",
+        "algorithmic_flops_per_call": sal["jacobi_flops"],
+        "note": "12*mr flops per pair visit times the sweeps of each rotating slice of both "
+                "blurs; duration = whole Salinas sp-w-product deblurring call"}
     if cpu is not None:
         line["cpu_baseline"] = {
             "value": cpu["ms"], "unit": "ms", "cores": host_threads(), "kind": "oracle",
@@ -652,7 +673,10 @@ def table1_report(torch, wp, dev, args):
             if gemm == "native":
                 row["speedup_vs_paper_cpu"] = round(PAPER_TABLE1_W_S[e - 1] / (ms * 1e-3), 1)
                 if p <= 256:
-                    ref = oracle.w_product(a.double().cpu().numpy(), b.double().cpu().numpy(), e)
+                    ah_, bh_ = a.double().cpu().numpy(), b.double().cpu().numpy()
+                    t0 = time.perf_counter()
+                    ref = oracle.w_product(ah_, bh_, e)
+                    row["oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
                     got = c.double().cpu().numpy()
                     row["fp32_rel_err_vs_oracle"] = float(np.linalg.norm((got - ref).ravel())
                                                           / np.linalg.norm(ref.ravel()))
@@ -660,8 +684,11 @@ def table1_report(torch, wp, dev, args):
         rows.append(row)
         del a, b
         torch.cuda.empty_cache()
+    top = rows[-1]
+    eff = 2.0 * 1024 ** 4 / (top["bf16x3_ms"] * 1e-3) / 1e12
     line = {
         "metric": "w-product time of p x p x p tensors (the shapes of Table 1), L = log2 p",
+        "value": top["bf16x3_ms"],
         "unit": "ms",
         "n_gpus": 1,
         "steps": max(args.steps, 1),
@@ -671,6 +698,15 @@ def table1_report(torch, wp, dev, args):
         "config": {"workload": "w-product A *_w B, A, B p x p x p, p = 2..1024, L = log2 p, "
                                "FP32 and bf16x3 face-products"},
         "rows": rows,
+        "roofline": {"bound": "mfma", "achieved": round(eff, 1), "peak": round(BF16_PEAK_TFS / 3, 1),
+                     "unit": "TFLOP/s", "frac": round(eff / (BF16_PEAK_TFS / 3), 4),
+                     "traffic": None,
+                     "kernel": "face_bf16_direct (bf16x3), p = 1024: whole w_product call",
+                     "note": "effective 2 p^4 flops per call; peak = BF16 dense MFMA / 3 products"},
+        "cpu_baseline": {"value": rows[7]["oracle_ms"], "unit": "ms", "cores": host_threads(),
+                         "kind": "oracle",
+                         "sample": "FP64 NumPy oracle of the p = 256 product (one call); "
+                                   "value is for p = 256, not the p = 1024 of `value`"},
         "note": "paper_cpu_w_product_s is the paper's own CPU timing (other hardware), context only",
     }
     print(json.dumps(line), flush=True)
@@ -823,6 +859,15 @@ def configs_report(torch, wp, synth, dev, args):
         "results": out,
     }
     print(json.dumps(line), flush=True)
+
+
+def jacobi_flops(info, mr, nc):
+    """Algorithmic flops of one-sided Jacobi: 12 * mr per pair visit (three dot
+    products and the rotation), nc (nc - 1) / 2 pairs per sweep, summed over
+    the slices that rotated (a slice that converged in its first sweep without
+    a rotation, such as an all-zero slice, is not counted)."""
+    sw = np.abs(np.asarray(info, dtype=np.int64))
+    return float(12.0 * mr * (nc * (nc - 1) / 2) * sw[sw > 1].sum())
 
 
 def host_threads():

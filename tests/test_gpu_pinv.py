@@ -172,3 +172,21 @@ def test_pinv_deblur_salinas_shape_sampled(wp):
         want = np.linalg.solve(tv, np.linalg.solve(th, bhat[c].T).T)
         assert rel_fro(xhat[c], want) <= max(n1, n2) * kap * EPS64
     assert np.abs(xhat[p >> L:]).max() <= 1e-12 * np.abs(xhat).max()
+
+
+def test_pinv_botswana_shape_sampled(wp):
+    # Botswana-sized blur (1476 x 1476 per slice, the 8-column-block path of
+    # the block Jacobi), 144 bands, L = 4, sparse: the kept s_4 slices of A_V^+
+    # equal numpy's pinv of the blur matrix, the dropped details are zero.
+    import torch
+    from paper_2601_08228_amd import synth
+    p, n, L = 144, 1476, 4
+    tv = synth.toeplitz_blur(n, 10)
+    av = torch.from_numpy(synth.stack_slices(tv, p)).cuda()
+    pv, iv = wp.w_pinv(av, L, sparse=True)
+    torch.cuda.synchronize()
+    assert host(iv).min() > 0
+    ref = np.linalg.pinv(tv)
+    tol = n * _kappa(tv[None], 0) * EPS64
+    for c in (0, 77, 143):
+        assert rel_fro(pv[c].cpu().numpy(), ref) <= tol

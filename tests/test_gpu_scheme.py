@@ -148,3 +148,20 @@ def test_derivative_vs_oracle(wp, gemm, dtype, tol):
     assert rel_fro(host(c), orc.w_product_scheme(a, b, L, taps)) <= tol
     assert rel_fro(host(at.grad), da) <= tol
     assert rel_fro(host(bt.grad), db) <= tol
+
+
+def test_full_size_passes_sampled(wp):
+    # The benchmark's tensor and launch shape (512x512x256 FP32, L = 4, CDF 5/3):
+    # every pass checked on 1024 sampled tubes, which the oracle computes one
+    # by one (a tube's transform involves that tube only).
+    import torch
+    from paper_2601_08228_amd import synth
+    L = 4
+    taps = orc.cdf53_scheme(L)
+    x = synth.normal_device((256, 512, 512), 21, torch.device("cuda:0"))
+    cols = np.random.default_rng(12).choice(512 * 512, size=1024, replace=False)
+    idx = torch.as_tensor(cols, device=x.device)
+    xs = x.reshape(256, -1)[:, idx].double().cpu().numpy()
+    for kind in KINDS:
+        got = wp.w_transform_scheme(x, L, taps, kind).reshape(256, -1)[:, idx]
+        assert rel_fro(host(got), _oracle_pass(xs, L, taps, kind)) <= 1e-6, kind
