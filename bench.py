@@ -843,11 +843,22 @@ def configs_report(torch, wp, synth, dev, args):
         xs, losses = deblur.solve(tk, ty, L, steps, eta, gemm=gemm)
         e1.record()
         torch.cuda.synchronize()
+        solver = deblur.GraphedSolver(tk, ty, L, eta, gemm=gemm)
+        torch.cuda.synchronize()
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record()
+        xg = solver.run(steps)
+        g1.record()
+        torch.cuda.synchronize()
         solves["fp32" if gemm == "native" else gemm] = {
             "ms_per_step": round(e0.elapsed_time(e1) / steps, 4),
+            "graphed_ms_per_step": round(g0.elapsed_time(g1) / steps, 4),
+            "graphed_equals_eager": bool(torch.equal(xg, xs)),
             "loss_first": losses[0], "loss_last": losses[-1],
             "loss_rel_err_vs_oracle_max": max(abs(l1 - l2) / l2 for l1, l2 in zip(losses, loss_ref)),
             "rel_err_X50_vs_oracle": rel(xs.cpu().numpy(), x_ref)}
+        del solver
     out["deblur_256x256x128_L3_50_steps"] = {"solves": solves, "oracle_s": round(oracle_s, 2),
                                              "eta": eta}
     line = {

@@ -104,3 +104,27 @@ def test_deblur_trajectory(wp, gemm):
     assert rel_fro(host(xs), x_ref) <= 1e-5
     np.testing.assert_allclose(losses, loss_ref[:len(losses)], rtol=1e-4)
     assert losses[-1] < losses[0]
+
+
+@pytest.mark.parametrize("gemm", ["native", "bf16x3"])
+def test_graphed_solve_matches_eager_every_replay(wp, gemm):
+    # The captured step, replayed with eager steps and synchronisations in
+    # between, gives the eager iterate bit for bit after every replay (same
+    # kernels in the same order), and the loss still falls.
+    import torch
+    from paper_2601_08228_amd import deblur
+    from paper_2601_08228_amd.autograd import WProduct
+    k, x, y, eta = _deblur_problem(32, 64, seed=7)
+    tk, ty = to_dev(k, torch.float32), to_dev(y, torch.float32)
+    solver = deblur.GraphedSolver(tk, ty, 3, eta, gemm=gemm)
+    xe = torch.zeros_like(ty)
+    loss0 = solver.residual_norm2()
+    for step in range(6):
+        solver.run(1)
+        xv = xe.clone().requires_grad_(True)
+        c = WProduct.apply(tk, xv, 3, gemm)
+        (g,) = torch.autograd.grad(c, xv, grad_outputs=2.0 * (c - ty))
+        xe = (xv - eta * g).detach()
+        torch.cuda.synchronize()
+        assert torch.equal(solver.x.detach(), xe), step
+    assert solver.residual_norm2() < loss0
