@@ -889,6 +889,26 @@ def host_threads():
         return int(os.cpu_count())
 
 
+def host_info():
+    """CPU model, visible cores and the BLAS NumPy calls (for the oracle timings)."""
+    info = {"cpu_count": os.cpu_count(), "cpu_model": None, "blas": None}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    info["cpu_model"] = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cfg = np.show_config(mode="dicts")
+        blas = cfg.get("Build Dependencies", {}).get("blas", {})
+        info["blas"] = "%s %s" % (blas.get("name", "?"), blas.get("version", ""))
+    except Exception:  # older NumPy without the dict form
+        pass
+    return info
+
+
 def measured_traffic():
     """HBM bytes per launch from the committed rocprofv3 counter summary.
 
@@ -947,6 +967,7 @@ def cpu_baseline(torch, a, b, g, c_gpu, da_gpu, x_hsi, svd_res):
                   % (t1 - t0, t3 - t2),
         "seconds": round(t1 - t0, 3),
         "w_svd_seconds": round(t3 - t2, 3),
+        "host": host_info(),
         "rel_err_gpu_vs_oracle": {
             "C_bf16x3": rel(c_gpu.double().cpu().numpy(), c_ref),
             "dA_bf16x3": rel(da_gpu.double().cpu().numpy(), da_ref),

@@ -991,8 +991,9 @@ __global__ __launch_bounds__(256) void max_reduce_kernel(const double* __restric
 // columns fit (each of up to 32 units of 16 lanes owns J slots, J the
 // smallest power of two with 32 * J >= nc_pad / 2, rpl rows per lane) and
 // there are enough slices to occupy the chip with one workgroup each (64 or
-// more, or narrow slices); the block kernel, which spreads a slice over
-// several workgroups, otherwise.
+// more), or the slices are too narrow (under 64 columns, at most two block
+// pairs) to spread; the block kernel, which spreads a slice over several
+// workgroups, otherwise.
 // Slice count from which one workgroup per slice beats the block kernel
 // (measured: 6 slices of 256 x 192 run 1.8x faster in the block kernel, 96
 // take the same time both ways, 192 of 256 x 256 run 1.4x faster in the
@@ -1016,7 +1017,7 @@ inline JacobiChoice choose_jacobi(int mr, int nc, size_t es, int64_t nsl) {
   c.rpl = 1;
   while (c.rpl * 16 < mr) c.rpl *= 2;
   c.reg = c.rpl <= 16 && c.J <= 4 && (es == 4 || (c.rpl <= 8 && c.J * c.rpl <= 16)) &&
-          (nsl >= kRegMinSlices || nc < 32);
+          (nsl >= kRegMinSlices || nc < 64);
   c.bj = bj_shape(mr, nc);
   return c;
 }
