@@ -12,6 +12,7 @@ import pytest
 
 import oracle as orc
 from gpu_helpers import device, to_dev, host, rel_fro
+from pins import load_golden
 
 pytestmark = pytest.mark.gpu
 
@@ -190,3 +191,20 @@ def test_pinv_botswana_shape_sampled(wp):
     tol = n * _kappa(tv[None], 0) * EPS64
     for c in (0, 77, 143):
         assert rel_fro(pv[c].cpu().numpy(), ref) <= tol
+
+
+def test_remark_2_2_printed_values(wp):
+    # The example after Remark 2.2: (A *_w B)^+ and B^+ *_w A^+ for A (2x3x2),
+    # B (3x2x2), L = 1, computed on the GPU (FP64) against the printed tensors
+    # C and D; B's detail slice has rank 1 (one singular value cut).
+    import torch
+    rm = load_golden("remark_2_2.json")
+    a, b = to_dev(rm["A"], torch.float64), to_dev(rm["B"], torch.float64)
+    c, _ = wp.w_pinv(wp.w_product(a, b, 1), 1)
+    ap, _ = wp.w_pinv(a, 1)
+    bp, _ = wp.w_pinv(b, 1)
+    d = wp.w_product(bp, ap, 1)
+    np.testing.assert_allclose(host(c), rm["C"], atol=1e-12)
+    np.testing.assert_allclose(host(d), rm["D"], atol=1e-12)
+    np.testing.assert_allclose(host(wp.w_transform(ap, 1))[0], rm["Apinv_s"], atol=1e-12)
+    np.testing.assert_allclose(host(wp.w_transform(bp, 1))[1], rm["Bpinv_d"], atol=1e-12)
