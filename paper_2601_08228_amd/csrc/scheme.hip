@@ -221,6 +221,7 @@ hipError_t launch_one(const T* in, T* out, uint16_t* hi, uint16_t* lo, int64_t P
   if (vec) return launch_v<T, V, K, SPLIT>(in, out, hi, lo, P, p, L, taps, s);
   return launch_v<T, 1, K, SPLIT>(in, out, hi, lo, P, p, L, taps, s);
 }
+
 template <typename T>
 hipError_t dispatch(LiftKind kind, const T* in, T* out, int64_t P, int64_t p, int L,
                     const SchemeTaps& taps, hipStream_t s) {
