@@ -107,6 +107,42 @@ def test_nonfinite_input_terminates(wp):
     assert info[1] > 0 and info[3] > 0
 
 
+def test_block_kernel_nonconvergence_is_reported(wp):
+    # The block kernel (300 rows in FP64) with a one-sweep limit: info = -1 for
+    # every slice, and the call returns.
+    import torch
+    a = np.random.default_rng(3).standard_normal((4, 300, 80))
+    res = wp.w_svd(to_dev(a, torch.float64), 2, 5, max_sweeps=1)
+    torch.cuda.synchronize()
+    assert np.all(host(res.info) == -1)
+
+
+def test_block_kernel_nonfinite_input_terminates(wp):
+    import torch
+    a = np.random.default_rng(4).standard_normal((4, 300, 70))
+    a[1, 100, 7] = np.inf
+    res = wp.w_svd(to_dev(a, torch.float64), 1, 3)
+    torch.cuda.synchronize()
+    info = host(res.info)
+    assert info[0] < 0 and info[2] < 0          # the coefficient slices that mix slice 1
+    assert info[1] > 0 and info[3] > 0
+
+
+def test_block_kernel_zero_slices(wp):
+    # Identical frontal slices: the detail coefficient slices are zero, skipped
+    # by the block kernel (one sweep, converged), with zero singular values.
+    import torch
+    m = np.random.default_rng(5).standard_normal((300, 70))
+    a = np.stack([m] * 4)
+    res = wp.w_svd(to_dev(a, torch.float64), 2, 6)
+    torch.cuda.synchronize()
+    info, sh = host(res.info), host(res.shat)
+    assert info.min() > 0 and np.all(info[1:] == 1)
+    assert np.all(sh[1:] == 0)
+    np.testing.assert_allclose(sh[0], np.linalg.svd(m, compute_uv=False)[:6], rtol=1e-12)
+    assert rel_fro(host(res.ak), orc.w_svd(a, 2, 6)[3]) <= 1e-12
+
+
 @pytest.mark.parametrize("shape,k", [((16, 100, 60), 10), ((8, 33, 64), 8), ((4, 256, 256), 20),
                                      ((4, 600, 300), 20), ((4, 1200, 90), 12)])
 def test_f32_shapes(wp, shape, k):
