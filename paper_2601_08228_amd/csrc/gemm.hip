@@ -445,18 +445,20 @@ __global__ __launch_bounds__(64 * Cfg::WM * Cfg::WN, 1) void face_gemm_kernel(Ge
 // lane), so several K stages can be in flight: stage t is consumed while
 // stages t+1 .. t+S-1 load.  Each operand keeps its stored layout in LDS:
 //   * K contiguous in memory ("KC": A not transposed, B transposed): LDS rows
-//     of BK = 16 K values (32 bytes); chunk c (8 values) of row r sits at
-//     chunk c ^ (((r >> 2) ^ (r >> 3)) & 1), so the fragment reads of 8 or 16
-//     consecutive rows cover disjoint banks;
-//   * K slow in memory ("KS"): LDS rows are the 16 K values' rows of 256
+//     of BK = 32 K values (64 bytes, one global load of 4 lanes per row);
+//     chunk c (8 values) of row r sits at chunk c ^ ((r >> 2) & 3), so the
+//     fragment reads of 8 or 16 consecutive rows cover disjoint banks;
+//   * K slow in memory ("KS"): LDS rows are the 32 K values' rows of 256
 //     elements (512 bytes); chunk c of K-row k sits at c ^ h(k), h(k) = 0, 6,
 //     10, 12 for k mod 4 = 0..3; fragments are read with ds_read_b64_tr_b16,
 //     which hands lane j of each 16-lane group element [k0 + q][r0 + j]
 //     (q = 0..3) when lane i addresses [k0 + i/4][r0 + 4 (i mod 4)].
+// A stage holds two MFMA K steps of 16; each plane is filled by two copies per
+// lane (rows 0-127 and 128-255, or K-rows 0-15 and 16-31), 8 KiB each.
 // Lanes outside the matrix get an offset past the buffer's end, so the
 // hardware returns zeros for them.
 namespace dl {
-constexpr int BM = 256, BN = 256, BK = 16, TM = 32;
+constexpr int BM = 256, BN = 256, BK = 32, TM = 32;
 constexpr int WN = 4, MT = 4, NT = 2;
 constexpr int THREADS = 512;
 constexpr int PLANE = 256 * BK * 2;  // bytes of one operand plane of one stage
@@ -466,7 +468,7 @@ constexpr uint32_t kOut = 0x80000000u;  // buffer offset that reads as zero
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_t;
 
-__device__ __forceinline__ int kc_chunk(int row, int c) { return c ^ (((row >> 2) ^ (row >> 3)) & 1); }
+__device__ __forceinline__ int kc_chunk(int row, int c) { return c ^ ((row >> 2) & 3); }
 __device__ __forceinline__ int ks_h(int k) { return (0x0C0A0600 >> (8 * (k & 3))) & 0xFF; }
 
 // s_waitcnt with only the vector-memory counter limited to n (gfx9 encoding:
@@ -501,12 +503,12 @@ struct DlSrc {
 
 template <bool KC>
 __device__ __forceinline__ DlSrc dl_src(const uint16_t* plane, int64_t ld, int r0, int rtot,
-                                        int kk) {
+                                        int kk, int i) {
   DlSrc d;
   const int t = threadIdx.x;
   if constexpr (KC) {
-    const int r = t >> 1;
-    const int c = kc_chunk(r, t & 1);
+    const int r = (t >> 2) + 128 * i;
+    const int c = kc_chunk(r, t & 3);
     d.base = uint32_t(((int64_t(r0) + r) * ld + 8 * c) * 2);
     d.kstep = 2;
     d.kidx = 8 * c;
@@ -514,7 +516,7 @@ __device__ __forceinline__ DlSrc dl_src(const uint16_t* plane, int64_t ld, int r
     d.rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(plane), 0,
                                                int(int64_t(rtot) * ld * 2), 0x00020000);
   } else {
-    const int k = t >> 5;
+    const int k = (t >> 5) + 16 * i;
     const int c = (t & 31) ^ ks_h(k);
     d.base = uint32_t((int64_t(k) * ld + r0 + 8 * c) * 2);
     d.kstep = uint32_t(ld * 2);
@@ -527,6 +529,7 @@ __device__ __forceinline__ DlSrc dl_src(const uint16_t* plane, int64_t ld, int r
 }
 
 __device__ __forceinline__ void dl_issue(const DlSrc& d, char* lds_plane, int k0, int kk) {
+  // (lds_plane: the 8 KiB half of the plane that this copy fills)
   const bool ok = d.rok && (k0 + d.kidx < kk);
   const uint32_t off = ok ? d.base + uint32_t(k0) * d.kstep : dl::kOut;
   // Each wavefront fills 1 KiB of the plane: lane l writes bytes 16 l of it.
@@ -543,10 +546,14 @@ __device__ __forceinline__ void dl_issue(const DlSrc& d, char* lds_plane, int k0
 // buffer-to-LDS copy writes, so for reads it can see it would wait for every
 // copy in flight (vmcnt(0)), which would undo the multi-stage pipeline.  The
 // copies a stage depends on are waited for explicitly before the barrier.
+// The outputs are early-clobber: a read's data can land while later reads of
+// the same block still need their address registers.
 
 // Per-lane byte offset, inside a stage buffer, of the lane's 16-byte K-chunk of
 // tile row xb + (l & 31) in a K-contiguous plane (MFMA operand layout: K
-// values 8 (l >> 5) .. +7).  Tiles 32 rows apart differ by 1024 bytes.
+// values 8 (l >> 5) .. +7 of the stage's first K step; the second step's
+// chunk is two further, at this offset ^ 32).  Tiles 32 rows apart differ by
+// 2048 bytes.
 __device__ __forceinline__ uint32_t kc_lane_off() {
   const int l = threadIdx.x & 63;
   const int row = l & 31;
@@ -555,7 +562,8 @@ __device__ __forceinline__ uint32_t kc_lane_off() {
 
 // Per-lane byte offset of a K-slow plane's transposed read: lane i of 16-lane
 // group g addresses K-row 8 (g >> 1) + 4 half + i / 4, columns
-// xb + 16 (g & 1) + 4 (i mod 4) .. +3.
+// xb + 16 (g & 1) + 4 (i mod 4) .. +3 (the stage's second K step: 16 K-rows,
+// 8 KiB, further).
 __device__ __forceinline__ uint32_t ks_lane_off(int xb, int half) {
   const int l = threadIdx.x & 63;
   const int g = l >> 4, i = l & 15;
@@ -564,89 +572,104 @@ __device__ __forceinline__ uint32_t ks_lane_off(int xb, int half) {
   return uint32_t(k * (dl::BM * 2) + 16 * ((r >> 3) ^ ks_h(k)) + 8 * (i & 1));
 }
 
-#define WP_KC2 "ds_read_b128 %0, %4\n\tds_read_b128 %1, %4 offset:1024\n\t"
-// K-contiguous fragments: T tiles (32 rows apart) of NPL planes (8 KiB apart).
+// K-contiguous fragments: T tiles (32 rows apart) of NPL planes (16 KiB apart).
 template <int T, int NPL>
 __device__ __forceinline__ void kc_frags(uint32_t a, u32x4 (&f)[T * NPL]) {
   if constexpr (T == 2 && NPL == 1) {
-    asm volatile("ds_read_b128 %0, %2\n\tds_read_b128 %1, %2 offset:1024\n\ts_waitcnt lgkmcnt(0)"
-                 : "=v"(f[0]), "=v"(f[1]) : "v"(a) : "memory");
+    asm volatile("ds_read_b128 %0, %2\n\tds_read_b128 %1, %2 offset:2048\n\ts_waitcnt lgkmcnt(0)"
+                 : "=&v"(f[0]), "=&v"(f[1]) : "v"(a) : "memory");
   } else if constexpr (T == 2 && NPL == 2) {
-    asm volatile("ds_read_b128 %0, %4\n\tds_read_b128 %1, %4 offset:1024\n\t"
-                 "ds_read_b128 %2, %4 offset:8192\n\tds_read_b128 %3, %4 offset:9216\n\t"
+    asm volatile("ds_read_b128 %0, %4\n\tds_read_b128 %1, %4 offset:2048\n\t"
+                 "ds_read_b128 %2, %4 offset:16384\n\tds_read_b128 %3, %4 offset:18432\n\t"
                  "s_waitcnt lgkmcnt(0)"
-                 : "=v"(f[0]), "=v"(f[1]), "=v"(f[2]), "=v"(f[3]) : "v"(a) : "memory");
+                 : "=&v"(f[0]), "=&v"(f[1]), "=&v"(f[2]), "=&v"(f[3]) : "v"(a) : "memory");
   } else if constexpr (T == 4 && NPL == 1) {
-    asm volatile("ds_read_b128 %0, %4\n\tds_read_b128 %1, %4 offset:1024\n\t"
-                 "ds_read_b128 %2, %4 offset:2048\n\tds_read_b128 %3, %4 offset:3072\n\t"
+    asm volatile("ds_read_b128 %0, %4\n\tds_read_b128 %1, %4 offset:2048\n\t"
+                 "ds_read_b128 %2, %4 offset:4096\n\tds_read_b128 %3, %4 offset:6144\n\t"
                  "s_waitcnt lgkmcnt(0)"
-                 : "=v"(f[0]), "=v"(f[1]), "=v"(f[2]), "=v"(f[3]) : "v"(a) : "memory");
+                 : "=&v"(f[0]), "=&v"(f[1]), "=&v"(f[2]), "=&v"(f[3]) : "v"(a) : "memory");
   } else {
     static_assert(T == 4 && NPL == 2, "unsupported fragment count");
-    asm volatile("ds_read_b128 %0, %8\n\tds_read_b128 %1, %8 offset:1024\n\t"
-                 "ds_read_b128 %2, %8 offset:2048\n\tds_read_b128 %3, %8 offset:3072\n\t"
-                 "ds_read_b128 %4, %8 offset:8192\n\tds_read_b128 %5, %8 offset:9216\n\t"
-                 "ds_read_b128 %6, %8 offset:10240\n\tds_read_b128 %7, %8 offset:11264\n\t"
+    asm volatile("ds_read_b128 %0, %8\n\tds_read_b128 %1, %8 offset:2048\n\t"
+                 "ds_read_b128 %2, %8 offset:4096\n\tds_read_b128 %3, %8 offset:6144\n\t"
+                 "ds_read_b128 %4, %8 offset:16384\n\tds_read_b128 %5, %8 offset:18432\n\t"
+                 "ds_read_b128 %6, %8 offset:20480\n\tds_read_b128 %7, %8 offset:22528\n\t"
                  "s_waitcnt lgkmcnt(0)"
-                 : "=v"(f[0]), "=v"(f[1]), "=v"(f[2]), "=v"(f[3]), "=v"(f[4]), "=v"(f[5]),
-                   "=v"(f[6]), "=v"(f[7])
+                 : "=&v"(f[0]), "=&v"(f[1]), "=&v"(f[2]), "=&v"(f[3]), "=&v"(f[4]), "=&v"(f[5]),
+                   "=&v"(f[6]), "=&v"(f[7])
                  : "v"(a) : "memory");
   }
 }
-#undef WP_KC2
 
 // K-slow fragments by transposed reads: addresses ad[2 t + half] for tile t,
-// plane p at + 8 KiB p; output h[(p T + t) 2 + half] holds 4 K values.
-template <int T, int NPL>
+// plane p at + PLANE p, all at the immediate offset OFF (the K step of the
+// stage); output h[(p T + t) 2 + half] holds 4 K values.
+template <int T, int NPL, int OFF>
 __device__ __forceinline__ void ks_frags(const uint32_t (&ad)[2 * T], u32x2 (&h)[2 * T * NPL]) {
   if constexpr (T == 2 && NPL == 1) {
-    asm volatile("ds_read_b64_tr_b16 %0, %4\n\tds_read_b64_tr_b16 %1, %5\n\t"
-                 "ds_read_b64_tr_b16 %2, %6\n\tds_read_b64_tr_b16 %3, %7\n\t"
+    asm volatile(
+                 "ds_read_b64_tr_b16 %[h0], %[a0] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h1], %[a1] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h2], %[a2] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h3], %[a3] offset:%[o0]\n\t"
                  "s_waitcnt lgkmcnt(0)"
-                 : "=v"(h[0]), "=v"(h[1]), "=v"(h[2]), "=v"(h[3])
-                 : "v"(ad[0]), "v"(ad[1]), "v"(ad[2]), "v"(ad[3]) : "memory");
+                 : [h0] "=&v"(h[0]), [h1] "=&v"(h[1]), [h2] "=&v"(h[2]), [h3] "=&v"(h[3])
+                 : [a0] "v"(ad[0]), [a1] "v"(ad[1]), [a2] "v"(ad[2]), [a3] "v"(ad[3]), [o0] "i"(OFF), [o1] "i"(OFF + dl::PLANE) : "memory");
   } else if constexpr (T == 2 && NPL == 2) {
-    asm volatile("ds_read_b64_tr_b16 %0, %8\n\tds_read_b64_tr_b16 %1, %9\n\t"
-                 "ds_read_b64_tr_b16 %2, %10\n\tds_read_b64_tr_b16 %3, %11\n\t"
-                 "ds_read_b64_tr_b16 %4, %8 offset:8192\n\tds_read_b64_tr_b16 %5, %9 offset:8192\n\t"
-                 "ds_read_b64_tr_b16 %6, %10 offset:8192\n\tds_read_b64_tr_b16 %7, %11 offset:8192\n\t"
+    asm volatile(
+                 "ds_read_b64_tr_b16 %[h0], %[a0] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h1], %[a1] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h2], %[a2] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h3], %[a3] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h4], %[a0] offset:%[o1]\n\t"
+                 "ds_read_b64_tr_b16 %[h5], %[a1] offset:%[o1]\n\t"
+                 "ds_read_b64_tr_b16 %[h6], %[a2] offset:%[o1]\n\t"
+                 "ds_read_b64_tr_b16 %[h7], %[a3] offset:%[o1]\n\t"
                  "s_waitcnt lgkmcnt(0)"
-                 : "=v"(h[0]), "=v"(h[1]), "=v"(h[2]), "=v"(h[3]), "=v"(h[4]), "=v"(h[5]),
-                   "=v"(h[6]), "=v"(h[7])
-                 : "v"(ad[0]), "v"(ad[1]), "v"(ad[2]), "v"(ad[3]) : "memory");
+                 : [h0] "=&v"(h[0]), [h1] "=&v"(h[1]), [h2] "=&v"(h[2]), [h3] "=&v"(h[3]), [h4] "=&v"(h[4]), [h5] "=&v"(h[5]), [h6] "=&v"(h[6]), [h7] "=&v"(h[7])
+                 : [a0] "v"(ad[0]), [a1] "v"(ad[1]), [a2] "v"(ad[2]), [a3] "v"(ad[3]), [o0] "i"(OFF), [o1] "i"(OFF + dl::PLANE) : "memory");
   } else if constexpr (T == 4 && NPL == 1) {
-    asm volatile("ds_read_b64_tr_b16 %0, %8\n\tds_read_b64_tr_b16 %1, %9\n\t"
-                 "ds_read_b64_tr_b16 %2, %10\n\tds_read_b64_tr_b16 %3, %11\n\t"
-                 "ds_read_b64_tr_b16 %4, %12\n\tds_read_b64_tr_b16 %5, %13\n\t"
-                 "ds_read_b64_tr_b16 %6, %14\n\tds_read_b64_tr_b16 %7, %15\n\t"
+    asm volatile(
+                 "ds_read_b64_tr_b16 %[h0], %[a0] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h1], %[a1] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h2], %[a2] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h3], %[a3] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h4], %[a4] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h5], %[a5] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h6], %[a6] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h7], %[a7] offset:%[o0]\n\t"
                  "s_waitcnt lgkmcnt(0)"
-                 : "=v"(h[0]), "=v"(h[1]), "=v"(h[2]), "=v"(h[3]), "=v"(h[4]), "=v"(h[5]),
-                   "=v"(h[6]), "=v"(h[7])
-                 : "v"(ad[0]), "v"(ad[1]), "v"(ad[2]), "v"(ad[3]), "v"(ad[4]), "v"(ad[5]),
-                   "v"(ad[6]), "v"(ad[7]) : "memory");
+                 : [h0] "=&v"(h[0]), [h1] "=&v"(h[1]), [h2] "=&v"(h[2]), [h3] "=&v"(h[3]), [h4] "=&v"(h[4]), [h5] "=&v"(h[5]), [h6] "=&v"(h[6]), [h7] "=&v"(h[7])
+                 : [a0] "v"(ad[0]), [a1] "v"(ad[1]), [a2] "v"(ad[2]), [a3] "v"(ad[3]), [a4] "v"(ad[4]), [a5] "v"(ad[5]), [a6] "v"(ad[6]), [a7] "v"(ad[7]), [o0] "i"(OFF), [o1] "i"(OFF + dl::PLANE) : "memory");
   } else {
     static_assert(T == 4 && NPL == 2, "unsupported fragment count");
-    asm volatile("ds_read_b64_tr_b16 %0, %16\n\tds_read_b64_tr_b16 %1, %17\n\t"
-                 "ds_read_b64_tr_b16 %2, %18\n\tds_read_b64_tr_b16 %3, %19\n\t"
-                 "ds_read_b64_tr_b16 %4, %20\n\tds_read_b64_tr_b16 %5, %21\n\t"
-                 "ds_read_b64_tr_b16 %6, %22\n\tds_read_b64_tr_b16 %7, %23\n\t"
-                 "ds_read_b64_tr_b16 %8, %16 offset:8192\n\tds_read_b64_tr_b16 %9, %17 offset:8192\n\t"
-                 "ds_read_b64_tr_b16 %10, %18 offset:8192\n\tds_read_b64_tr_b16 %11, %19 offset:8192\n\t"
-                 "ds_read_b64_tr_b16 %12, %20 offset:8192\n\tds_read_b64_tr_b16 %13, %21 offset:8192\n\t"
-                 "ds_read_b64_tr_b16 %14, %22 offset:8192\n\tds_read_b64_tr_b16 %15, %23 offset:8192\n\t"
+    asm volatile(
+                 "ds_read_b64_tr_b16 %[h0], %[a0] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h1], %[a1] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h2], %[a2] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h3], %[a3] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h4], %[a4] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h5], %[a5] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h6], %[a6] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h7], %[a7] offset:%[o0]\n\t"
+                 "ds_read_b64_tr_b16 %[h8], %[a0] offset:%[o1]\n\t"
+                 "ds_read_b64_tr_b16 %[h9], %[a1] offset:%[o1]\n\t"
+                 "ds_read_b64_tr_b16 %[h10], %[a2] offset:%[o1]\n\t"
+                 "ds_read_b64_tr_b16 %[h11], %[a3] offset:%[o1]\n\t"
+                 "ds_read_b64_tr_b16 %[h12], %[a4] offset:%[o1]\n\t"
+                 "ds_read_b64_tr_b16 %[h13], %[a5] offset:%[o1]\n\t"
+                 "ds_read_b64_tr_b16 %[h14], %[a6] offset:%[o1]\n\t"
+                 "ds_read_b64_tr_b16 %[h15], %[a7] offset:%[o1]\n\t"
                  "s_waitcnt lgkmcnt(0)"
-                 : "=v"(h[0]), "=v"(h[1]), "=v"(h[2]), "=v"(h[3]), "=v"(h[4]), "=v"(h[5]),
-                   "=v"(h[6]), "=v"(h[7]), "=v"(h[8]), "=v"(h[9]), "=v"(h[10]), "=v"(h[11]),
-                   "=v"(h[12]), "=v"(h[13]), "=v"(h[14]), "=v"(h[15])
-                 : "v"(ad[0]), "v"(ad[1]), "v"(ad[2]), "v"(ad[3]), "v"(ad[4]), "v"(ad[5]),
-                   "v"(ad[6]), "v"(ad[7]) : "memory");
+                 : [h0] "=&v"(h[0]), [h1] "=&v"(h[1]), [h2] "=&v"(h[2]), [h3] "=&v"(h[3]), [h4] "=&v"(h[4]), [h5] "=&v"(h[5]), [h6] "=&v"(h[6]), [h7] "=&v"(h[7]), [h8] "=&v"(h[8]), [h9] "=&v"(h[9]), [h10] "=&v"(h[10]), [h11] "=&v"(h[11]), [h12] "=&v"(h[12]), [h13] "=&v"(h[13]), [h14] "=&v"(h[14]), [h15] "=&v"(h[15])
+                 : [a0] "v"(ad[0]), [a1] "v"(ad[1]), [a2] "v"(ad[2]), [a3] "v"(ad[3]), [a4] "v"(ad[4]), [a5] "v"(ad[5]), [a6] "v"(ad[6]), [a7] "v"(ad[7]), [o0] "i"(OFF), [o1] "i"(OFF + dl::PLANE) : "memory");
   }
 }
 
 // All fragments of one operand for one stage: T tiles of NPL planes, tile t of
 // plane p in f[p T + t].  KC: lane_off = kc_lane_off(); KS: ks_off[2 t + half]
 // = ks_lane_off(xb + 32 t, half).
-template <bool KC, int T, int NPL>
+template <bool KC, int T, int NPL, int OFF>
 __device__ __forceinline__ void stage_frags(uint32_t buf, uint32_t kc_off, const uint32_t (&ks_off)[2 * T],
                                             u32x4 (&f)[T * NPL]) {
   if constexpr (KC) {
@@ -656,7 +679,7 @@ __device__ __forceinline__ void stage_frags(uint32_t buf, uint32_t kc_off, const
 #pragma unroll
     for (int q = 0; q < 2 * T; ++q) ad[q] = buf + ks_off[q];
     u32x2 h[2 * T * NPL];
-    ks_frags<T, NPL>(ad, h);
+    ks_frags<T, NPL, OFF>(ad, h);
 #pragma unroll
     for (int q = 0; q < T * NPL; ++q) {
       f[q][0] = h[2 * q][0];
@@ -705,20 +728,24 @@ __global__ __launch_bounds__(dl::THREADS, 1) void face_bf16_direct(GemmArgs args
                            X3 ? static_cast<const uint16_t*>(args.a_lo) + slice * args.sa : nullptr};
   const uint16_t* pb[2] = {static_cast<const uint16_t*>(args.b_hi) + slice * args.sb,
                            X3 ? static_cast<const uint16_t*>(args.b_lo) + slice * args.sb : nullptr};
-  DlSrc sa[NPL], sb[NPL];
+  DlSrc sa[NPL][2], sb[NPL][2];
 #pragma unroll
-  for (int q = 0; q < NPL; ++q) {
-    sa[q] = dl_src<A_KC>(pa[q], args.lda, m0, args.m, kk);
-    sb[q] = dl_src<B_KC>(pb[q], args.ldb, n0, args.n, kk);
-  }
+  for (int q = 0; q < NPL; ++q)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      sa[q][i] = dl_src<A_KC>(pa[q], args.lda, m0, args.m, kk, i);
+      sb[q][i] = dl_src<B_KC>(pb[q], args.ldb, n0, args.n, kk, i);
+    }
   // Copies of K stage st into stage buffer B.
   auto issue = [&](auto BB, int st) {
     char* base = dl_stage<decltype(BB)::value, STAGE>();
 #pragma unroll
-    for (int q = 0; q < NPL; ++q) {
-      dl_issue(sa[q], base + q * PLANE, st * BK, kk);
-      dl_issue(sb[q], base + (NPL + q) * PLANE, st * BK, kk);
-    }
+    for (int q = 0; q < NPL; ++q)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        dl_issue(sa[q][i], base + q * PLANE + i * (PLANE / 2), st * BK, kk);
+        dl_issue(sb[q][i], base + (NPL + q) * PLANE + i * (PLANE / 2), st * BK, kk);
+      }
   };
 
   const int lane = threadIdx.x & 63;
@@ -764,24 +791,30 @@ __global__ __launch_bounds__(dl::THREADS, 1) void face_bf16_direct(GemmArgs args
       if (t >= nk) return;
       // Stage t has landed once at most the stages issued after it are pending.
       const int pending = (nk - 1 < t + S - 2 ? nk - 1 : t + S - 2) - t;
-      wait_stages<S, 2 * NPL>(pending);
+      wait_stages<S, 4 * NPL>(pending);
       dl_barrier();  // every wave's copies of stage t are in LDS; stage t-1 is consumed
       if (t + S - 1 < nk) issue(std::integral_constant<int, (u + S - 1) % S>{}, t + S - 1);
 
       const uint32_t buf = lds_addr(dl_stage<u, STAGE>());
-      u32x4 fa[MT * NPL], fb[NT * NPL];
-      stage_frags<B_KC, NT, NPL>(buf + NPL * PLANE, b_kc_off, b_ks_off, fb);
-      stage_frags<A_KC, MT, NPL>(buf, a_kc_off, a_ks_off, fa);
+      // Two MFMA K steps of 16 per stage: the K-contiguous fragments of the
+      // second sit at the lane offset ^ 32, the K-slow ones 16 K-rows (8 KiB)
+      // further.
+      static_for_n<2>([&](auto HH) {
+        constexpr int h = decltype(HH)::value;
+        u32x4 fa[MT * NPL], fb[NT * NPL];
+        stage_frags<B_KC, NT, NPL, h * PLANE / 2>(buf + NPL * PLANE, b_kc_off ^ (32 * h), b_ks_off, fb);
+        stage_frags<A_KC, MT, NPL, h * PLANE / 2>(buf, a_kc_off ^ (32 * h), a_ks_off, fa);
 #pragma unroll
-      for (int i = 0; i < MT; ++i)
+        for (int i = 0; i < MT; ++i)
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-          if constexpr (X3) {
-            mma_bf16(fa[MT + i], fb[j], acc[i][j]);
-            mma_bf16(fa[i], fb[NT + j], acc[i][j]);
+          for (int j = 0; j < NT; ++j) {
+            if constexpr (X3) {
+              mma_bf16(fa[MT + i], fb[j], acc[i][j]);
+              mma_bf16(fa[i], fb[NT + j], acc[i][j]);
+            }
+            mma_bf16(fa[i], fb[j], acc[i][j]);
           }
-          mma_bf16(fa[i], fb[j], acc[i][j]);
-        }
+      });
     });
   }
 
@@ -826,7 +859,7 @@ inline bool direct_ok(const GemmArgs& a, bool ta, bool tb) {
 
 template <bool X3>
 hipError_t dispatch_direct(const GemmArgs& a, bool ta, bool tb, hipStream_t s) {
-  constexpr int S = X3 ? 4 : 8;
+  constexpr int S = X3 ? 2 : 4;
   if (!ta && !tb) return launch_direct<false, false, X3, S>(a, s);
   if (ta && !tb) return launch_direct<true, false, X3, S>(a, s);
   if (!ta && tb) return launch_direct<false, true, X3, S>(a, s);
