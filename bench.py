@@ -236,12 +236,26 @@ def main():
                           "launches_per_step": launches, "ms_per_launch": round(per_launch_ms, 4),
                           "algorithmic_bytes_per_launch": bytes_per[name]}
         elif name.startswith("face"):
-            ach = flops / (per_launch_ms * 1e-3) / 1e12
-            peak = BF16_PEAK_TFS / 3.0  # three BF16 products per effective product
-            rows[name] = {"bound": "mfma", "achieved": round(ach, 2), "peak": round(peak, 1),
-                          "unit": "TFLOP/s", "frac": round(ach / peak, 4),
-                          "launches_per_step": launches, "ms_per_launch": round(per_launch_ms, 4),
-                          "algorithmic_flops_per_launch": flops}
+            # Both ceilings: three BF16 products per effective product on the
+            # matrix cores, and the bytes a launch must move (hi + lo parts of
+            # both operands read, the FP32 product written).  On this shape the
+            # bytes take longer at the HBM peak than the flops at the MFMA
+            # peak, so HBM is the binding bound.
+            peak = BF16_PEAK_TFS / 3.0
+            face_bytes = 4 * P * N1 * N2 + 4 * P * N2 * N3 + 4 * P * N1 * N3
+            t_flops = flops / (peak * 1e12)
+            t_bytes = face_bytes / (HBM_PEAK_GBS * 1e9)
+            ach_f = flops / (per_launch_ms * 1e-3) / 1e12
+            ach_b = face_bytes / (per_launch_ms * 1e-3) / 1e9
+            mfma = {"achieved": round(ach_f, 2), "peak": round(peak, 1), "unit": "TFLOP/s",
+                    "frac": round(ach_f / peak, 4), "algorithmic_flops_per_launch": flops}
+            hbm = {"achieved": round(ach_b, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": round(ach_b / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": face_bytes}
+            if t_bytes >= t_flops:
+                rows[name] = dict(bound="hbm", **hbm, mfma=mfma)
+            else:
+                rows[name] = dict(bound="mfma", **mfma, hbm=hbm)
+            rows[name].update(launches_per_step=launches, ms_per_launch=round(per_launch_ms, 4))
     # The Jacobi kernel dominates the step.  Its algorithmic work per pair visit
     # is 6*mr flops of dot products plus 6*mr of rotation; a sweep visits
     # nc(nc-1)/2 pairs; the sweeps are those the slices actually ran.  The

@@ -28,7 +28,7 @@ def _operands(p, m, k, n, ta, tb, seed, dist="normal"):
 # degenerate 1-wide dimensions, and K shorter than one K-tile.  The last two
 # have every dimension a multiple of 8, so the BF16 modes take the
 # direct-to-LDS kernel in all four transpose combinations (tails of 8 rows
-# and columns, K not a multiple of the 16-wide stage, many stages).
+# and columns, K not a multiple of the 32-wide stage, many stages).
 SHAPES = [(3, 130, 70, 200), (2, 64, 64, 64), (1, 1, 1, 1), (5, 17, 3, 9), (4, 257, 33, 129),
           (2, 300, 520, 260), (16, 32, 24, 20), (1, 7, 1000, 5), (2, 264, 200, 328),
           (1, 512, 1032, 256)]
@@ -92,6 +92,37 @@ def test_deterministic(wp):
     r1 = host(wp.w_face_product(da, db))
     r2 = host(wp.w_face_product(da, db))
     assert np.array_equal(r1, r2)
+
+
+@pytest.mark.parametrize("tt", TRANS)
+@pytest.mark.parametrize("mode", ["bf16", "bf16x3"])
+def test_direct_kernel_repeatable_full_size(wp, tt, mode):
+    # The benchmark shape (256 slices of 512x512x512) in every transpose
+    # combination: repeated calls give the same bits.  (A fragment read whose
+    # output shared a register with a later read's address once made the
+    # transposed-A BF16 kernel differ from call to call.)
+    import torch
+    from paper_2601_08228_amd import synth
+    dev = torch.device("cuda:0")
+    a = synth.normal_device((256, 512, 512), 41, dev)
+    b = synth.normal_device((256, 512, 512), 42, dev)
+    ahi, alo = wp.w_transform_split(a, 0)
+    bhi, blo = wp.w_transform_split(b, 0)
+    if mode == "bf16":
+        alo = blo = None
+    ref = wp.w_face_product_split(ahi, alo, bhi, blo, *tt, gemm=mode)
+    for _ in range(4):
+        assert torch.equal(wp.w_face_product_split(ahi, alo, bhi, blo, *tt, gemm=mode), ref)
+    # One sampled slice against the oracle's product of the same bf16 parts.
+    s = 97
+    ah = ahi[s].float().double().cpu().numpy()
+    bh = bhi[s].float().double().cpu().numpy()
+    exact = orc.face(ah[None], bh[None], *tt)[0]
+    if mode == "bf16x3":
+        al = alo[s].float().double().cpu().numpy()
+        bl = blo[s].float().double().cpu().numpy()
+        exact = exact + orc.face(ah[None], bl[None], *tt)[0] + orc.face(al[None], bh[None], *tt)[0]
+    assert rel_fro(ref[s].double().cpu().numpy(), exact) <= 1e-7 * np.sqrt(512)
 
 
 def test_unaligned_pitch_uses_scalar_loads(wp):
