@@ -623,15 +623,52 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
   const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
 
   T tc[J][RPL], bc[J][RPL];
+  // Columns of a row-major slice (no transpose) are strided in memory, and
+  // gathering them lane by lane fetches each line many times over; they go
+  // through LDS instead, half the rows at a time: coalesced row reads into
+  // the (not yet used) exchange buffer, then each lane picks its entries.
+  constexpr int CH = 8 * RPL;  // rows per half
+  const int ld = nc + 1;       // odd pitch: a unit's 16 rows hit 16 banks
+  const bool staged = !d.trans && RPL >= 2 &&
+                      CH * ld <= int(sizeof(s_x) / sizeof(T));
+  if (staged) {
+    T* stage = &s_x[0][0][0][0];
+    const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int it = top_id(q0 + j, 0), ib = bot_id(q0 + j, 0);
+    for (int half = 0; half < 2; ++half) {
+      const int r0 = half * CH;
+      for (int r = wave; r < CH; r += kJacobiWaves) {
+        const bool in = r0 + r < mr;
+        for (int c = lane; c < nc; c += 64) stage[r * ld + c] = in ? a[(r0 + r) * d.n2 + c] : T(0);
+      }
+      __syncthreads();
 #pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-      const int row = lane16 + 16 * t;
-      const bool ok = active && row < mr;
-      tc[j][t] = (ok && it < nc) ? w_src(row, it) : T(0);
-      bc[j][t] = (ok && ib < nc) ? w_src(row, ib) : T(0);
+      for (int j = 0; j < J; ++j) {
+        const int it = top_id(q0 + j, 0), ib = bot_id(q0 + j, 0);
+#pragma unroll
+        for (int t = half * (RPL / 2); t < (half + 1) * (RPL / 2); ++t) {
+          const int row = lane16 + 16 * t;
+          const bool ok = active && row < mr;
+          const int lr = row - r0;  // in [0, CH)
+          const T vt = stage[lr * ld + (it < nc ? it : 0)];
+          const T vb = stage[lr * ld + (ib < nc ? ib : 0)];
+          tc[j][t] = (ok && it < nc) ? vt : T(0);
+          bc[j][t] = (ok && ib < nc) ? vb : T(0);
+        }
+      }
+      __syncthreads();
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int it = top_id(q0 + j, 0), ib = bot_id(q0 + j, 0);
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int row = lane16 + 16 * t;
+        const bool ok = active && row < mr;
+        tc[j][t] = (ok && it < nc) ? w_src(row, it) : T(0);
+        bc[j][t] = (ok && ib < nc) ? w_src(row, ib) : T(0);
+      }
     }
   }
   if (threadIdx.x == 0) {
