@@ -373,6 +373,19 @@ def sparse_report(torch, wp, synth, dev, args):
     _, rs32 = time_call(lambda: wp.w_svd_sparse(x, T3_L, 32))
     sp_flops = jacobi_flops(rs32.info.cpu().numpy(), T3_N1, T3_N2)
     sp_ms = rows["32"]["sp_w_svd_ms"]
+    # The paper's Table 3 at the ranks measured here: t-svd, w-svd and sp-w-svd
+    # seconds for its three images (Coffee, Sugar-Salt-Flour, Yatsuhashi).
+    paper_t3 = {"2": ([5.0527, 5.1041, 5.0454], [0.8583, 0.8642, 0.8646], [0.0548, 0.0631, 0.0641]),
+                "8": ([5.1427, 5.1191, 5.1430], [0.8808, 0.8871, 0.8898], [0.0783, 0.0730, 0.0795]),
+                "32": ([5.1278, 5.1361, 5.1695], [0.9026, 0.8968, 0.8980], [0.0674, 0.0802, 0.0796]),
+                "64": ([5.1108, 5.1562, 5.1286], [0.8961, 0.9006, 0.9035], [0.0802, 0.0732, 0.0753])}
+    paper_table3 = {
+        "note": "the paper's own CPU timings (s) on three 256x192x96 NIR images (" + PAPER_HOST +
+                "); context only, the t-svd is not built here",
+        "by_rank": {rk: {"t_svd_s": t, "w_svd_s": w, "sp_w_svd_s": sp,
+                         "w_svd_speedup_vs_t_svd": [round(a / b, 2) for a, b in zip(t, w)],
+                         "sp_w_svd_speedup_vs_t_svd": [round(a / b, 2) for a, b in zip(t, sp)]}
+                    for rk, (t, w, sp) in paper_t3.items()}}
     line = {
         "metric": "sp-w-svd and w-svd time (FP32, 256x192x96 hyperspectral-like, L=5)",
         "value": rows["32"]["sp_w_svd_ms"],
@@ -388,6 +401,7 @@ def sparse_report(torch, wp, synth, dev, args):
                                "(12 components, noise 0.01), L=5, ranks 2/8/32/64; value at rank 32",
                    "n1": T3_N1, "n2": T3_N2, "p": T3_P, "L": T3_L},
         "ranks": rows,
+        "paper_table3": paper_table3,
         "roofline": {"bound": "alu", "achieved": round(sp_flops / sp_ms / 1e9, 2),
                      "peak": FP32_PEAK_TFS, "unit": "TFLOP/s",
                      "frac": round(sp_flops / sp_ms / 1e9 / FP32_PEAK_TFS, 4), "traffic": None,
@@ -410,6 +424,9 @@ def sparse_report(torch, wp, synth, dev, args):
 DEBLUR_CASES = [("PaviaU", 610, 340, 102, 1, 9.8508, 9.7492),
                 ("Salinas", 512, 217, 204, 2, 10.9848, 6.5197),
                 ("Botswana", 1476, 256, 144, 4, 40.5728, 7.3428)]
+# The same table's t-product times (s) and the PSNRs it reports (t-product, w-product).
+PAPER_TABLE4_T = {"PaviaU": (23.6328, 21.1510, 26.7206), "Salinas": (31.4715, 17.6921, 23.6444),
+                  "Botswana": (204.7620, 34.4265, 36.7636)}
 DEBLUR_B = 10
 
 
@@ -524,6 +541,15 @@ def deblur_report(torch, wp, synth, dev, args):
                                "value: Salinas, sp-w-product",
                    "blur_b": DEBLUR_B},
         "cases": cases,
+        "paper_table4": {
+            "note": "the paper's own CPU timings on the real images (" + PAPER_HOST + "); "
+                    "context only, the t-product is not built here",
+            "cases": {name: {"t_product_s": PAPER_TABLE4_T[name][0], "w_product_s": pw,
+                             "sp_w_product_s": ps,
+                             "sp_w_product_speedup_vs_t_product": round(PAPER_TABLE4_T[name][0] / ps, 2),
+                             "psnr_t_db": PAPER_TABLE4_T[name][1],
+                             "psnr_w_db": PAPER_TABLE4_T[name][2]}
+                      for name, _, _, _, _, pw, ps in DEBLUR_CASES}},
     }
     sal = cases["Salinas"]["sp_w_product"]
     line["roofline"] = {
@@ -648,6 +674,11 @@ def schemes_report(torch, wp, synth, dev, args):
 # The paper's Table 1 w-product times (seconds, CPU, mean of 10 runs), p = 2^1 .. 2^10.
 PAPER_TABLE1_W_S = [1.576734e-04, 1.577830e-04, 3.587484e-04, 4.789996e-04, 1.763617e-03,
                     8.662295e-03, 5.306451e-02, 3.919755e-01, 3.161437e+00, 7.749125e+01]
+# The same table's t-product times (seconds), for the paper's own t / w ratio.
+PAPER_TABLE1_T_S = [2.240753e-04, 3.964186e-04, 4.737735e-04, 6.299186e-04, 2.113118e-03,
+                    1.014814e-02, 7.131300e-02, 5.213821e-01, 4.842443e+00, 1.574944e+02]
+# Where the paper's timings were taken (Sec. III): context only.
+PAPER_HOST = "the paper's setup: Python 3.11 on an Intel Core i9-12900K (16 cores), CPU only"
 
 
 def table1_report(torch, wp, dev, args):
@@ -665,7 +696,9 @@ def table1_report(torch, wp, dev, args):
         g.manual_seed(1000 + e)
         a = torch.rand((p, p, p), generator=g, device=dev)
         b = torch.rand((p, p, p), generator=g, device=dev)
-        row = {"p": p, "L": e, "paper_cpu_w_product_s": PAPER_TABLE1_W_S[e - 1]}
+        row = {"p": p, "L": e, "paper_cpu_w_product_s": PAPER_TABLE1_W_S[e - 1],
+               "paper_cpu_t_product_s": PAPER_TABLE1_T_S[e - 1],
+               "paper_t_over_w": round(PAPER_TABLE1_T_S[e - 1] / PAPER_TABLE1_W_S[e - 1], 2)}
         for gemm in ("native", "bf16x3"):
             ws = torch.empty(max(wp.w_product_workspace(p, p, p, p, e, torch.float32, gemm), 1),
                              dtype=torch.uint8, device=dev)
@@ -721,7 +754,9 @@ def table1_report(torch, wp, dev, args):
                          "kind": "oracle",
                          "sample": "FP64 NumPy oracle of the p = 256 product (one call); "
                                    "value is for p = 256, not the p = 1024 of `value`"},
-        "note": "paper_cpu_w_product_s is the paper's own CPU timing (other hardware), context only",
+        "note": "paper_cpu_w_product_s / paper_cpu_t_product_s are the paper's own CPU timings "
+                "of the w-product and the t-product (Table 1; " + PAPER_HOST + "), context only; "
+                "the t-product is not built here",
     }
     print(json.dumps(line), flush=True)
 
