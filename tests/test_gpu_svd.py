@@ -161,6 +161,33 @@ def test_f32_shapes(wp, shape, k):
     assert host(res.orth_err).max() <= 1e-4
 
 
+# Register kernel with 64 or more slices of untransposed columns: the columns
+# are staged through LDS half a slice at a time.  Heights that fill the
+# second half only partly, odd column counts (a zero tournament column), both
+# precisions.
+@pytest.mark.parametrize("shape,dtype,k", [((64, 200, 150), "f32", 12), ((64, 129, 129), "f32", 9),
+                                           ((64, 120, 77), "f64", 7), ((64, 40, 33), "f64", 5)])
+def test_register_kernel_staged_columns(wp, shape, dtype, k):
+    import torch
+    p, n1, n2 = shape
+    L = 2
+    a = np.random.default_rng(n1 * 3 + n2).standard_normal(shape)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    if dtype == "f32":
+        a = cast(a, np.float32)
+    res = wp.w_svd(to_dev(a, td), L, k)
+    torch.cuda.synchronize()
+    assert host(res.info).min() > 0
+    _, sh_ref, _, ak_ref = orc.w_svd(a, L, k)
+    if dtype == "f64":
+        assert rel_fro(host(res.shat), sh_ref) <= 1e-12
+        assert rel_fro(host(res.ak), ak_ref) <= 1e-12
+    else:
+        assert rel_fro(host(res.shat), sh_ref) <= 1e-5
+        assert rel_fro(host(res.ak), ak_ref) <= 1e-4
+        assert host(res.orth_err).max() <= 1e-4
+
+
 # ---- sp-w-svd (Sec. IV-B): only s_L and d_L are decomposed ---------------------
 
 @pytest.mark.parametrize("shape,L,k", [((32, 20, 14), 3, 5), ((16, 7, 9), 4, 3),
