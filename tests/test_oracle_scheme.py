@@ -152,3 +152,19 @@ def test_scheme_vjp_by_finite_differences():
 def test_taps_shape_is_checked():
     with pytest.raises(ValueError):
         orc.lift_fwd_scheme(np.zeros((8, 2)), 2, np.zeros((1, 2, 5)))
+
+
+def test_scheme_matrix_by_hand_and_inverse():
+    # One lazy level on p = 4 (pairs (x0, x1), (x2, x3)): s = (x0 + x1) / 2,
+    # d = x0 - x1, coefficients in Mallat order (s_1 then d_1).
+    expect = np.array([[0.5, 0.5, 0.0, 0.0],
+                       [0.0, 0.0, 0.5, 0.5],
+                       [1.0, -1.0, 0.0, 0.0],
+                       [0.0, 0.0, 1.0, -1.0]])
+    np.testing.assert_array_equal(orc.scheme_matrix(4, 1, orc.lazy_scheme(1)), expect)
+    # Lemma 2.1 in matrix form, for any stencils: W^{-1} W = W W^{-1} = I.
+    t = _random_scheme(3, 21)
+    Wm = orc.scheme_matrix(16, 3, t)
+    Wi = orc.scheme_inverse_matrix(16, 3, t)
+    np.testing.assert_allclose(Wi @ Wm, np.eye(16), atol=1e-12)
+    np.testing.assert_allclose(Wm @ Wi, np.eye(16), atol=1e-12)
