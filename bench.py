@@ -42,6 +42,7 @@ SVD_P, SVD_N, SVD_L, SVD_K = 192, 256, 3, 20
 T3_N1, T3_N2, T3_P, T3_L, T3_RANKS = 256, 192, 96, 5, (2, 8, 32, 64)
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFS = 2500.0          # dense BF16 MFMA
+N_CUS = 256                 # MI355X compute units
 FP32_PEAK_TFS = 157.3
 FP64_VALU_PEAK_TFS = 78.6
 
@@ -373,6 +374,13 @@ def sparse_report(torch, wp, synth, dev, args):
     _, rs32 = time_call(lambda: wp.w_svd_sparse(x, T3_L, 32))
     sp_flops = jacobi_flops(rs32.info.cpu().numpy(), T3_N1, T3_N2)
     sp_ms = rows["32"]["sp_w_svd_ms"]
+    # Block Jacobi geometry of the call: blocks of 16 columns (8 beyond 1024
+    # rows), an even block count, one workgroup per block pair and slice.
+    sp_mr, sp_nc = max(T3_N1, T3_N2), min(T3_N1, T3_N2)
+    sp_b = 16 if sp_mr <= 1024 else 8
+    sp_nbp = -(-sp_nc // sp_b)
+    sp_nbp += sp_nbp % 2
+    sp_wgs = (sp_nbp // 2) * 2 * (T3_P >> T3_L)
     # The paper's Table 3 at the ranks measured here: t-svd, w-svd and sp-w-svd
     # seconds for its three images (Coffee, Sugar-Salt-Flour, Yatsuhashi).
     paper_t3 = {"2": ([5.0527, 5.1041, 5.0454], [0.8583, 0.8642, 0.8646], [0.0548, 0.0631, 0.0641]),
@@ -407,8 +415,14 @@ def sparse_report(torch, wp, synth, dev, args):
                      "frac": round(sp_flops / sp_ms / 1e9 / FP32_PEAK_TFS, 4), "traffic": None,
                      "kernel": "bj_round_kernel<float, 16, 8> (block Jacobi, 6 slices)",
                      "algorithmic_flops_per_call": sp_flops,
+                     "workgroups_per_launch": sp_wgs,
+                     "frac_of_occupied_cus": round(sp_flops / sp_ms / 1e9 / FP32_PEAK_TFS
+                                                   * N_CUS / min(N_CUS, sp_wgs), 4),
                      "note": "12*mr flops per pair visit times the sweeps of each slice; "
-                             "duration = whole sp-w-svd call at rank 32"},
+                             "duration = whole sp-w-svd call at rank 32; the 6 slices give "
+                             "the block Jacobi one workgroup per block pair, so a launch "
+                             "occupies workgroups_per_launch of the 256 CUs and the call is "
+                             "bound by its chain of dependent sub-rounds"},
         "cpu_baseline": {
             "value": cpu_ms["32"]["sp_w_svd"], "unit": "ms", "cores": host_threads(),
             "kind": "oracle",
