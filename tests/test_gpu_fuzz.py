@@ -5,7 +5,8 @@ position, L = 0, transposes, thin slices); these draw combinations of them at
 random from fixed seeds: p = m 2^L with L = 0..4, slice sides 1..70 (so the
 vector and scalar lifting paths, partial MFMA tiles and both Jacobi
 orientations all occur), both transpose flags and every precision mode, each
-against the oracle with the tolerance of its fixed-shape test.
+against the oracle with the tolerance of its fixed-shape test (and, where a
+draw falls outside an entry point's contract, its documented error).
 """
 
 import numpy as np
@@ -113,3 +114,27 @@ def test_scheme_passes(wp, case):
     for kind, fn in ref.items():
         got = host(wp.w_transform_scheme(to_dev(x, torch.float64), L, taps, kind))
         assert rel_fro(got, fn(x, L, taps)) <= 1e-13, (kind, p, n1, n2, L)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_pinv(wp, case):
+    # FP64 Moore-Penrose inverse, full and sparse (s_L, d_L only), against the
+    # oracle within max(n1, n2) * kappa * eps (kappa of the kept slices).
+    import torch
+    rng, p, n1, n2, _, L = _draw(600 + case)
+    a = rng.standard_normal((p, n1, n2))
+    kap = 1.0
+    for sl in orc.lift_fwd(a, L):
+        s = np.linalg.svd(sl, compute_uv=False)
+        kap = max(kap, s[0] / s[-1])
+    tol = max(n1, n2) * kap * np.finfo(np.float64).eps
+    for sparse, ref in ((False, orc.w_pinv), (True, orc.w_pinv_sparse)):
+        if sparse and L == 0:
+            # The sparse inverse keeps s_L and d_L, which needs a level.
+            from paper_2601_08228_amd._lib import WprodError
+            with pytest.raises(WprodError):
+                wp.w_pinv(to_dev(a, torch.float64), L, sparse=True)
+            continue
+        out, info = wp.w_pinv(to_dev(a, torch.float64), L, sparse=sparse)
+        assert host(info).min() > 0
+        assert rel_fro(host(out), ref(a, L)) <= tol, (sparse, p, n1, n2, L)
