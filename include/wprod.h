@@ -168,6 +168,22 @@ wp_status w_face_product_split(const uint16_t* a_hi, const uint16_t* a_lo,
                                int64_t n1, int64_t n2, int64_t n3, int64_t p,
                                int trans_a, int trans_b, int gemm, void* stream);
 
+/* One call for every arithmetic: gemm = WP_GEMM_NATIVE is w_face_product
+ * (ws may be NULL); WP_GEMM_BF16 / WP_GEMM_BF16X3 (float ah, bh, ch) first
+ * split both operands into bf16 hi / lo planes in ws (hi = bf16_rne(x),
+ * lo = bf16_rne(x - hi)), then run w_face_product_split.  ws (device, caller
+ * owned, any alignment) must hold w_face_product_workspace(...) bytes
+ * (WP_EWORKSPACE otherwise) and must not overlap ah, bh or ch (WP_EALIAS). */
+wp_status w_face_product_gemm(const void* ah, const void* bh, void* ch,
+                              int64_t n1, int64_t n2, int64_t n3, int64_t p,
+                              int trans_a, int trans_b, int dtype, int gemm,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for w_face_product_gemm: 0 for WP_GEMM_NATIVE (none needed)
+ * and on invalid arguments. */
+size_t w_face_product_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p,
+                                int dtype, int gemm);
+
 /* ---- w-product (Def. 2.1, Alg. 1) ------------------------------------------
  * C = op(A) *_w op(B) = W^{-1}( W(op A) Delta W(op B) ); C is (p, n1, n3).
  * gemm selects the face-product arithmetic (WP_GEMM_*; BF16 modes need
@@ -185,16 +201,31 @@ size_t w_product_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int L,
 
 /* ---- w-svd (Alg. 2, Thm 2.5) ------------------------------------------------
  * Truncated SVD of every coefficient slice of W(A), A (p, n1, n2), by one-sided
- * Jacobi with FP64 rotation parameters (dot products and angles in FP64; data
- * stays in `dtype`).  Outputs (wavelet-domain factors, Thm 2.5):
+ * Jacobi.  Precision: the rotation parameters (cosine and sine, from the
+ * tangent of the angle that zeroes the pair's inner product) are computed in
+ * FP64; the column norms and the inner product they come from are accumulated
+ * in the data type (FP32 sums of FP32 products for WP_F32, FP64 for WP_F64);
+ * the rotations are applied to the data in `dtype`.  The pair threshold is
+ * |w_i.w_j| > sqrt(max(n1, n2)) * u * |w_i| |w_j| (u = 2^-24 for F32, 2^-53 for
+ * F64); a slice has converged after a sweep with no rotation.  One factor is
+ * formed from the converged columns; the other is recovered from the slice
+ * (v_i = A^T u_i / sigma_i, or u_i = A v_i / sigma_i), accumulated in FP64,
+ * and orthonormalised by Newton-Schulz steps in FP64 until it is orthonormal
+ * to the rounding of `dtype` (at most 4 steps).  Outputs (wavelet-domain
+ * factors, Thm 2.5):
  *   uhat (p, n1, k), shat (p, k) descending and >= 0, vhat (p, n2, k),
  *   ak (p, n1, n2) = W^{-1}(uhat_k diag(shat_k) vhat_k^T), or NULL to skip.
+ * Numerical rank: a recovered column whose singular value is at or below
+ *   max(n1, n2) * u * shat[slice][0] (the default cut of w_pinv) is returned
+ *   zero, and so are the columns of zero singular values; they add nothing
+ *   to ak.
  * Signs: in each column of uhat the entry of largest magnitude is positive
  * (lowest row wins ties); the matching vhat column is flipped with it.
  * info (p int32, device): sweeps used by slice k if it converged, minus the
  *   sweeps run if it did not (max_sweeps reached, or a non-finite value met).
  * orth_err (2 doubles, device, or NULL): max over slices of
- *   max|uhat^T uhat - I| and of max|vhat^T vhat - I|, evaluated in FP64.
+ *   max|uhat^T uhat - I| and of max|vhat^T vhat - I|, evaluated in FP64 over
+ *   the columns that are not zero.
  * 1 <= k <= min(n1, n2); max_sweeps >= 1 (<= 0 selects 30 for F64, 20 for F32);
  * n1, n2 <= 2048.  ws must hold w_svd_workspace(...) bytes.
  */
@@ -205,6 +236,18 @@ wp_status w_svd(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k,
 
 /* Workspace bytes for w_svd (0 on invalid arguments). */
 size_t w_svd_workspace(int64_t n1, int64_t n2, int64_t p, int L, int k, int dtype);
+
+/* w_svd, with two caller-owned HIP events (hipEvent_t, created by the caller
+ * on the stream's device; either may be NULL) recorded on `stream` just before
+ * and just after the Jacobi stage (the sweeps, the singular values and the
+ * factor formed from the columns), so that hipEventElapsedTime times the
+ * decomposition alone.  All other arguments, results and errors as for w_svd;
+ * a failed hipEventRecord returns WP_ELAUNCH. */
+wp_status w_svd_timed(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k,
+                      void* uhat, void* shat, void* vhat, void* ak, int max_sweeps,
+                      int32_t* info, double* orth_err, int dtype,
+                      void* ws, size_t ws_bytes, void* stream,
+                      void* jacobi_begin, void* jacobi_end);
 
 /* ---- sp-w-svd (Sec. IV-B, computational analysis) ---------------------------
  * Sparse variant of w_svd: only the two coarsest coefficient blocks, s_L and

@@ -39,12 +39,17 @@ SIGNATURES = {
                                 _c_int, _vp]),
     "w_face_product_split": (_c_int, [_vp, _vp, _vp, _vp, _vp, _c_i64, _c_i64, _c_i64, _c_i64,
                                       _c_int, _c_int, _c_int, _vp]),
+    "w_face_product_gemm": (_c_int, [_vp, _vp, _vp, _c_i64, _c_i64, _c_i64, _c_i64, _c_int,
+                                     _c_int, _c_int, _c_int, _vp, _sz, _vp]),
+    "w_face_product_workspace": (_sz, [_c_i64, _c_i64, _c_i64, _c_i64, _c_int, _c_int]),
     "w_product": (_c_int, [_vp, _vp, _vp, _c_i64, _c_i64, _c_i64, _c_i64, _c_int, _c_int, _c_int,
                            _c_int, _c_int, _vp, _sz, _vp]),
     "w_product_workspace": (_sz, [_c_i64, _c_i64, _c_i64, _c_i64, _c_int, _c_int, _c_int]),
     "w_svd": (_c_int, [_vp, _c_i64, _c_i64, _c_i64, _c_int, _c_int, _vp, _vp, _vp, _vp, _c_int,
                        _vp, _vp, _c_int, _vp, _sz, _vp]),
     "w_svd_workspace": (_sz, [_c_i64, _c_i64, _c_i64, _c_int, _c_int, _c_int]),
+    "w_svd_timed": (_c_int, [_vp, _c_i64, _c_i64, _c_i64, _c_int, _c_int, _vp, _vp, _vp, _vp,
+                             _c_int, _vp, _vp, _c_int, _vp, _sz, _vp, _vp, _vp]),
     "w_svd_sparse": (_c_int, [_vp, _c_i64, _c_i64, _c_i64, _c_int, _c_int, _vp, _vp, _vp, _vp,
                               _c_int, _vp, _vp, _c_int, _vp, _sz, _vp]),
     "w_svd_sparse_workspace": (_sz, [_c_i64, _c_i64, _c_i64, _c_int, _c_int, _c_int]),

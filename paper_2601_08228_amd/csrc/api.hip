@@ -129,6 +129,25 @@ inline ProductPlan plan_product(const FaceShapes& fs, int dtype, int gemm) {
   return pl;
 }
 
+// Workspace layout of w_face_product_gemm: the bf16 planes of both operands
+// (no transformed C; native mode needs no workspace).
+inline ProductPlan plan_face(const FaceShapes& fs, int gemm) {
+  ProductPlan pl{};
+  if (gemm == WP_GEMM_NATIVE) return pl;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = wp::align_up(off + bytes, kAlign);
+    return at;
+  };
+  pl.ah = take(size_t(fs.a) * 2);
+  pl.ah_lo = gemm == WP_GEMM_BF16X3 ? take(size_t(fs.a) * 2) : 0;
+  pl.bh = take(size_t(fs.b) * 2);
+  pl.bh_lo = gemm == WP_GEMM_BF16X3 ? take(size_t(fs.b) * 2) : 0;
+  pl.total = off + kAlign;
+  return pl;
+}
+
 // Host taps (L levels x {predict, update} x 5) into the kernel argument; every
 // tap finite.  L = 0 needs no taps.
 inline wp_status load_taps(const double* taps, int L, wp::SchemeTaps* out) {
@@ -252,6 +271,51 @@ wp_status w_face_product_split(const uint16_t* a_hi, const uint16_t* a_lo, const
     return WP_EALIAS;
   return from_hip(wp::launch_face_bf16(a_hi, a_lo, b_hi, b_lo, ch, n1, n2, n3, p, trans_a != 0,
                                        trans_b != 0, x3, static_cast<hipStream_t>(stream)));
+}
+
+size_t w_face_product_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int dtype,
+                                int gemm) {
+  if (check_modes(dtype, gemm) != WP_OK) return 0;
+  FaceShapes fs{};
+  if (check_face(n1, n2, n3, p, 0, 0, &fs) != WP_OK) return 0;
+  return plan_face(fs, gemm).total;
+}
+
+wp_status w_face_product_gemm(const void* ah, const void* bh, void* ch, int64_t n1, int64_t n2,
+                              int64_t n3, int64_t p, int trans_a, int trans_b, int dtype,
+                              int gemm, void* ws, size_t ws_bytes, void* stream) {
+  wp_status st = check_modes(dtype, gemm);
+  if (st != WP_OK) return st;
+  if (gemm == WP_GEMM_NATIVE)
+    return w_face_product(ah, bh, ch, n1, n2, n3, p, trans_a, trans_b, dtype, stream);
+  FaceShapes fs{};
+  st = check_face(n1, n2, n3, p, trans_a, trans_b, &fs);
+  if (st != WP_OK) return st;
+  if (ah == nullptr || bh == nullptr || ch == nullptr || ws == nullptr) return WP_ENULL;
+  const ProductPlan pl = plan_face(fs, gemm);
+  if (ws_bytes < pl.total) return WP_EWORKSPACE;
+  const Range ra = range_of(ah, fs.a, 4), rb = range_of(bh, fs.b, 4), rc = range_of(ch, fs.c, 4);
+  const Range rw{static_cast<const char*>(ws), static_cast<const char*>(ws) + ws_bytes};
+  if (overlap(rc, ra) || overlap(rc, rb) || overlap(rw, ra) || overlap(rw, rb) || overlap(rw, rc))
+    return WP_EALIAS;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = reinterpret_cast<char*>(wp::align_up(reinterpret_cast<uintptr_t>(ws), kAlign));
+  const bool x3 = gemm == WP_GEMM_BF16X3;
+  uint16_t* ahi = reinterpret_cast<uint16_t*>(base + pl.ah);
+  uint16_t* alo = x3 ? reinterpret_cast<uint16_t*>(base + pl.ah_lo) : nullptr;
+  uint16_t* bhi = reinterpret_cast<uint16_t*>(base + pl.bh);
+  uint16_t* blo = x3 ? reinterpret_cast<uint16_t*>(base + pl.bh_lo) : nullptr;
+  // The split is elementwise: the identity transform (L = 0) with the
+  // split epilogue, over whatever stored shape the operands have.
+  hipError_t e = wp::launch_lift_f32_split(LiftKind::kForward, static_cast<const float*>(ah), ahi,
+                                           alo, n1 * n2, p, 0, s);
+  if (e == hipSuccess)
+    e = wp::launch_lift_f32_split(LiftKind::kForward, static_cast<const float*>(bh), bhi, blo,
+                                  n2 * n3, p, 0, s);
+  if (e == hipSuccess)
+    e = wp::launch_face_bf16(ahi, alo, bhi, blo, static_cast<float*>(ch), n1, n2, n3, p,
+                             trans_a != 0, trans_b != 0, x3, s);
+  return from_hip(e);
 }
 
 size_t w_product_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int L, int dtype,
@@ -446,7 +510,8 @@ wp_status check_svd(int64_t n1, int64_t n2, int64_t p, int L, int k, bool sparse
 wp_status run_svd_entry(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k,
                         bool sparse, void* uhat, void* shat, void* vhat, void* ak,
                         int max_sweeps, int32_t* info, double* orth_err, int dtype, void* ws,
-                        size_t ws_bytes, void* stream) {
+                        size_t ws_bytes, void* stream, void* ev_begin = nullptr,
+                        void* ev_end = nullptr) {
   int64_t elems = 0, nsl = 0;
   const wp_status st = check_svd(n1, n2, p, L, k, sparse, dtype, &elems, &nsl);
   if (st != WP_OK) return st;
@@ -468,7 +533,8 @@ wp_status run_svd_entry(const void* a, int64_t n1, int64_t n2, int64_t p, int L,
       if (overlap(outs[i], outs[j])) return WP_EALIAS;
   }
   return from_hip(wp::launch_svd(a, n1, n2, p, L, k, sparse, uhat, shat, vhat, ak, max_sweeps,
-                                 info, orth_err, dtype, ws, static_cast<hipStream_t>(stream)));
+                                 info, orth_err, dtype, ws, static_cast<hipStream_t>(stream),
+                                 static_cast<hipEvent_t>(ev_begin), static_cast<hipEvent_t>(ev_end)));
 }
 
 }  // namespace
@@ -486,6 +552,14 @@ wp_status w_svd(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
                 int dtype, void* ws, size_t ws_bytes, void* stream) {
   return run_svd_entry(a, n1, n2, p, L, k, false, uhat, shat, vhat, ak, max_sweeps, info,
                        orth_err, dtype, ws, ws_bytes, stream);
+}
+
+wp_status w_svd_timed(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k,
+                      void* uhat, void* shat, void* vhat, void* ak, int max_sweeps,
+                      int32_t* info, double* orth_err, int dtype, void* ws, size_t ws_bytes,
+                      void* stream, void* jacobi_begin, void* jacobi_end) {
+  return run_svd_entry(a, n1, n2, p, L, k, false, uhat, shat, vhat, ak, max_sweeps, info,
+                       orth_err, dtype, ws, ws_bytes, stream, jacobi_begin, jacobi_end);
 }
 
 size_t w_svd_sparse_workspace(int64_t n1, int64_t n2, int64_t p, int L, int k, int dtype) {

@@ -32,6 +32,8 @@
 
 #include <type_traits>
 
+#include <atomic>
+
 #include "wp_internal.h"
 
 namespace wp {
@@ -876,12 +878,19 @@ hipError_t launch_cfg(const GemmArgs& a0, hipStream_t s) {
   if (total == 0) return hipSuccess;
   if (total > 0x7fffffff) return hipErrorInvalidConfiguration;
   auto kern = face_gemm_kernel<Cfg, TA, TB, X3>;
-  static bool attr_set = false;  // per instantiation; setting it twice is harmless
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, D::LDS_BYTES);
+  // The LDS limit is an attribute of the kernel on each device: set it once
+  // per instantiation and device (setting it twice is harmless, so a race
+  // between host threads costs at most one extra call).
+  constexpr int kMaxDevices = 64;
+  static std::atomic<bool> attr_set[kMaxDevices];
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices || !attr_set[dev].load(std::memory_order_acquire)) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, D::LDS_BYTES);
     if (e != hipSuccess) return e;
-    attr_set = true;
+    if (dev >= 0 && dev < kMaxDevices) attr_set[dev].store(true, std::memory_order_release);
   }
   hipLaunchKernelGGL(kern, dim3(unsigned(total)), dim3(D::THREADS), D::LDS_BYTES, s, a);
   return hipGetLastError();

@@ -2,17 +2,17 @@
 // one-sided (Hestenes) Jacobi, rank-k rebuild on the face-product GEMM, and
 // the inverse lifting.
 //
-// Jacobi: one workgroup owns one coefficient slice, viewed as a matrix W with
-// mr = max(n1, n2) rows and nc = min(n1, n2) columns (the slice itself when
-// n1 >= n2, its transpose otherwise); V starts as the identity.  A sweep
-// visits every column pair once, as a round-robin tournament: nc_pad - 1
-// rounds of nc_pad / 2 disjoint pairs.  For each pair, alpha = |w_i|^2,
-// beta = |w_j|^2 and gamma = w_i.w_j are formed (in FP64 for FP64 data; for
-// FP32 data in FP32 by the register-resident kernel and in FP64 by the
-// general one), and when |gamma| > tol * sqrt(alpha * beta) (tol = sqrt(mr) *
-// unit roundoff of the data type) the rotation angle is computed in FP64 and
-// the rotation is applied to columns i, j of W (and V) in the data type.  A
-// slice has converged after a sweep without rotation.
+// Jacobi: a coefficient slice is viewed as a matrix W with mr = max(n1, n2)
+// rows and nc = min(n1, n2) columns (the slice itself when n1 >= n2, its
+// transpose otherwise).  A sweep visits every column pair once, as a
+// round-robin tournament: nc_pad - 1 rounds of nc_pad / 2 disjoint pairs.  For
+// each pair, alpha = |w_i|^2, beta = |w_j|^2 and gamma = w_i.w_j are summed in
+// the data type (FP32 lane partials and FP32 cross-lane sums for FP32 data,
+// FP64 throughout for FP64 data; FP64 sums of FP32 data measured 1.6x slower
+// for the same sweeps and errors), and when |gamma| > tol * sqrt(alpha * beta)
+// (tol = sqrt(mr) * unit roundoff of the data type) the rotation parameters
+// are computed in FP64 and the rotation is applied to columns i, j of W in
+// the data type.  A slice has converged after a sweep without rotation.
 //
 // Register-resident kernel (the columns of a slice fit the registers of one
 // workgroup): 32 units of 16 lanes each hold J tournament slots (a top and a
@@ -21,8 +21,9 @@
 // evaluated side by side in FP64 and broadcast, and the circle advance of
 // the round-robin tournament is a renaming of register slots plus two
 // columns per unit through LDS.  Only W is kept; the second factor is
-// recovered from A V = U Sigma afterwards and orthonormalised.  A general
-// kernel keeps W and V in the workspace and covers the larger shapes.
+// recovered from A V = U Sigma afterwards and orthonormalised.  A block
+// kernel spreads a slice over many workgroups and covers the larger shapes
+// and the calls with few slices; it keeps only W as well.
 //
 // sp-w-svd (Sec. IV-B) runs the same kernels on the s_L and d_L slices only
 // and leaves the finer details zero in the rebuild.
@@ -818,7 +819,7 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
 // accumulated in FP64 from the coefficients.  In the second case the sign
 // convention (largest |U| entry positive) is applied here to both columns,
 // and U * sigma is written for the rebuild.  One workgroup per (slice, i);
-// columns with sigma_i = 0 come out zero.
+// columns with sigma_i at or below max(n1, n2) u sigma_1 come out zero.
 template <typename T>
 __global__ __launch_bounds__(256) void recover_kernel(const T* __restrict__ ah, SvdDims d,
                                                       T* __restrict__ uhat,
@@ -838,8 +839,12 @@ __global__ __launch_bounds__(256) void recover_kernel(const T* __restrict__ ah, 
   __shared__ double s_best[256];
   __shared__ int s_row[256];
   __shared__ double s_val[256];
+  // Columns of singular values at or below the numerical rank cut
+  // max(n1, n2) u sigma_1 (the cut of the pseudo-inverse) are not recovered
+  // (zero): A^T u_i / sigma_i would amplify the rounding of u_i beyond one.
   const double sg = double(shat[int64_t(slice) * k + i]);
-  const double inv = sg > 0 ? 1.0 / sg : 0.0;
+  const double cut = double(mr) * Unit<T>::value * double(shat[int64_t(slice) * k]);
+  const double inv = sg > cut ? 1.0 / sg : 0.0;
   for (int t = threadIdx.x; t < mr; t += 256) s_src[t] = double(src[int64_t(t) * k + i]);
   __syncthreads();
   double out[kOut];
@@ -899,7 +904,8 @@ __global__ __launch_bounds__(256) void recover_kernel(const T* __restrict__ ah, 
 
 // Gram matrix G = X^T X (FP64) of one slice X (n x k row-major, k <= 64) for
 // 256 threads: thread t accumulates entries e = t + 256 q (a = e / k, b = e % k)
-// in acc[q]; rows are staged through LDS in blocks of kGramRows as FP64.
+// in acc[q]; rows are staged through LDS in blocks of kGramRows as FP64, so n
+// is unbounded.
 constexpr int kGramRows = 64;
 template <typename T>
 __device__ __forceinline__ void gram_k64(const T* __restrict__ X, int n, int k, double (&acc)[16],
@@ -925,82 +931,244 @@ __device__ __forceinline__ void gram_k64(const T* __restrict__ X, int n, int k, 
   }
 }
 
-// One Newton-Schulz step of the polar iteration, X <- X (3I - X^T X) / 2 =
-// X - X E / 2 with E = X^T X - I, for the recovered factor X (one slice (n, k)
-// row-major per workgroup): the recovery inherits the error of U amplified by
-// sigma_1 / sigma_i, and this step removes its non-orthogonality to second
-// order.  FP64 Gram, k <= 64; X is staged in LDS (n <= 256 rows for FP32
-// data, 128 for FP64: the register-resident Jacobi's limits).
-template <typename T>
-__global__ __launch_bounds__(256) void polish_kernel(T* __restrict__ x, int n, int k) {
-  constexpr int kRows = sizeof(T) == 8 ? 128 : 256;
-  __shared__ double s_e[64 * 64];
-  __shared__ double s_blk[kGramRows * 64];
-  __shared__ T s_xs[kRows * 64];
-  if (n > kRows || k > 64) return;  // the host launches it only within these limits
-  T* X = x + int64_t(blockIdx.x) * n * k;
-  double acc[16];
-  gram_k64<T>(X, n, k, acc, s_blk);
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int e = threadIdx.x + 256 * q;
-    if (e < k * k) s_e[e] = acc[q] - ((e / k) == (e % k) ? 1.0 : 0.0);
-  }
-  for (int e = threadIdx.x; e < n * k; e += 256) s_xs[e] = X[e];
-  __syncthreads();
-  // Entry (r, i): X[r][i] - 0.5 * sum_j X[r][j] E[j][i]; consecutive threads
-  // take consecutive i, so E reads are conflict-free and X reads broadcast.
-  for (int e = threadIdx.x; e < n * k; e += 256) {
-    const int r = e / k, i = e - r * k;
-    const T* xr = s_xs + r * k;
-    double acc2 = 0;
-    for (int j = 0; j < k; ++j) acc2 = fma(double(xr[j]), s_e[j * k + i], acc2);
-    X[e] = T(double(xr[i]) - 0.5 * acc2);
-  }
-}
-
-// max |X^T X - I| over the k x k Gram matrix of one slice of X (n x k, row-major), FP64.
-template <typename T>
-__global__ __launch_bounds__(256) void orth_kernel(const T* __restrict__ x, int n, int k,
-                                                   double* __restrict__ part) {
-  const int slice = blockIdx.x;
-  const T* X = x + int64_t(slice) * n * k;
+// Largest |G_ab - delta_ab| over the columns a, b that are not identically
+// zero (G_aa > 0), NaN-propagating; every thread of the 256 returns it.
+// Columns that are zero belong to singular values at or below the numerical
+// rank cut and are left out of the orthogonality measure.
+__device__ __forceinline__ double gram_dev(const double* __restrict__ G, int k, double* red) {
   double worst = 0;
-  if (k <= 64) {
-    __shared__ double s_blk[kGramRows * 64];
-    double acc[16];
-    gram_k64<T>(X, n, k, acc, s_blk);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = threadIdx.x + 256 * q;
-      if (e < k * k) {
-        const double dev = fabs(acc[q] - ((e / k) == (e % k) ? 1.0 : 0.0));
-        worst = (dev > worst || dev != dev) ? dev : worst;
-      }
-    }
-  } else {
-    for (int e = threadIdx.x; e < k * k; e += 256) {
-      const int a = e / k, b = e % k;
-      if (b < a) continue;
-      double acc = 0;
-      for (int r = 0; r < n; ++r)
-        acc = fma(double(X[int64_t(r) * k + a]), double(X[int64_t(r) * k + b]), acc);
-      const double dev = fabs(acc - (a == b ? 1.0 : 0.0));
-      worst = (dev > worst || dev != dev) ? dev : worst;
-    }
+  for (int e = threadIdx.x; e < k * k; e += 256) {
+    const int a = e / k, b = e - a * k;
+    if (G[int64_t(a) * k + a] == 0.0 || G[int64_t(b) * k + b] == 0.0) continue;
+    const double dev = fabs(G[e] - (a == b ? 1.0 : 0.0));
+    worst = (dev > worst || dev != dev) ? dev : worst;
   }
-  __shared__ double red[256];
+  __syncthreads();
   red[threadIdx.x] = worst;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      const double o = red[threadIdx.x + s];
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double o = red[threadIdx.x + w];
       const double m = red[threadIdx.x];
       red[threadIdx.x] = (o > m || o != o) ? o : m;
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[slice] = red[0];
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Newton-Schulz polish of the recovered factor X (n x k per slice, row-major):
+// the polar iteration X <- X (3 I - X^T X) / 2 = X M, M = 1.5 I - 0.5 G, in
+// FP64 from the stored values.  The recovery inherits the error of the
+// Jacobi-formed factor amplified by sigma_1 / sigma_i, and each step squares
+// the deviation from orthonormality (e -> ~0.75 e^2), so the loop stops when
+// the deviation is at the rounding level of T (no step) or after the step
+// taken from a deviation below sqrt(u_T) / 4, and takes at most kPolishSteps
+// steps.  Zero columns (singular values at or below the numerical rank cut)
+// stay zero: their rows and columns of G are zero, so M maps them to zero and
+// adds nothing to the others.
+constexpr int kPolishSteps = 4;
+
+// Deviation thresholds of the polish for n rows of T: at or below t_done the
+// factor is orthonormal to the rounding of T; from at or below t_last one
+// more step reaches it.
+template <typename T>
+__host__ __device__ inline void polish_thresholds(int n, double& t_done, double& t_last) {
+  const double u = Unit<T>::value;
+  t_done = 4.0 * (sqrt(double(n)) + 2.0) * u;
+  t_last = 0.25 * sqrt(u);
+}
+
+// k <= 64: one workgroup per slice, G and M in LDS, the rows of X streamed
+// through LDS in blocks (each row's update reads only that row, so the blocks
+// are updated in place).
+template <typename T>
+__global__ __launch_bounds__(256) void polish_kernel(T* __restrict__ x, int n, int k) {
+  __shared__ double s_m[64 * 64];
+  __shared__ double s_blk[kGramRows * 64];
+  __shared__ double s_red[256];
+  T* X = x + int64_t(blockIdx.x) * n * k;
+  double t_done, t_last;
+  polish_thresholds<T>(n, t_done, t_last);
+  for (int step = 0; step < kPolishSteps; ++step) {
+    double acc[16];
+    gram_k64<T>(X, n, k, acc, s_blk);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      if (e < k * k) s_m[e] = acc[q];
+    }
+    __syncthreads();
+    const double dev = gram_dev(s_m, k, s_red);
+    if (dev <= t_done) return;
+    for (int e = threadIdx.x; e < k * k; e += 256) {
+      const int a = e / k, b = e - a * k;
+      s_m[e] = (a == b ? 1.5 : 0.0) - 0.5 * s_m[e];
+    }
+    // Row blocks: stage, then X[r][i] = sum_j X[r][j] M[j][i]; consecutive
+    // threads take consecutive i, so M reads are conflict-free and X reads
+    // broadcast.
+    for (int r0 = 0; r0 < n; r0 += kGramRows) {
+      const int rows = n - r0 < kGramRows ? n - r0 : kGramRows;
+      T* Xb = X + int64_t(r0) * k;
+      __syncthreads();
+      for (int e = threadIdx.x; e < rows * k; e += 256) s_blk[e] = double(Xb[e]);
+      __syncthreads();
+      for (int e = threadIdx.x; e < rows * k; e += 256) {
+        const int r = e / k, i = e - r * k;
+        const double* xr = s_blk + r * k;
+        double acc2 = 0;
+        for (int j = 0; j < k; ++j) acc2 = fma(xr[j], s_m[j * k + i], acc2);
+        Xb[e] = T(acc2);
+      }
+    }
+    if (!(dev > t_last)) return;  // NaN: stop as well
+  }
+}
+
+// Per-slice C = op(A) B with FP64 accumulation, a small helper GEMM of the
+// polish and the orthogonality check for k > 64 (off the benchmark path).
+// op(A) is m x kk: A stored kk x m (row-major) when TRA, m x kk otherwise; B
+// is kk x n and C m x n, row-major; slices at strides sa, sb, sc.  A 64 x 64
+// tile of C per workgroup (4 x 4 per thread), kk in chunks of 16 through LDS.
+// Slices whose state is 1 are skipped.
+template <typename TA, typename TB, typename TC, bool TRA>
+__global__ __launch_bounds__(256) void small_gemm_kernel(const TA* __restrict__ a,
+                                                         const TB* __restrict__ b,
+                                                         TC* __restrict__ c, int m, int kk, int n,
+                                                         int64_t sa, int64_t sb, int64_t sc,
+                                                         const int* __restrict__ state) {
+  const int slice = blockIdx.z;
+  if (state != nullptr && state[slice] == 1) return;
+  __shared__ double s_a[16][65];
+  __shared__ double s_b[16][65];
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  const TA* A = a + slice * sa;
+  const TB* B = b + slice * sb;
+  TC* C = c + slice * sc;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0;
+  for (int k0 = 0; k0 < kk; k0 += 16) {
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+      int kq, r;
+      if (TRA) {
+        kq = e >> 6;
+        r = e & 63;
+      } else {
+        r = e >> 4;
+        kq = e & 15;
+      }
+      const int gr = r0 + r, gk = k0 + kq;
+      double v = 0;
+      if (gr < m && gk < kk)
+        v = TRA ? double(A[int64_t(gk) * m + gr]) : double(A[int64_t(gr) * kk + gk]);
+      s_a[kq][r] = v;
+    }
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+      const int kq = e >> 6, cc = e & 63;
+      const int gk = k0 + kq, gc = c0 + cc;
+      s_b[kq][cc] = (gk < kk && gc < n) ? double(B[int64_t(gk) * n + gc]) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = s_a[q][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = s_b[q][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = r0 + ty + 16 * i;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int cc = c0 + tx + 16 * j;
+      if (r < m && cc < n) C[int64_t(r) * n + cc] = TC(acc[i][j]);
+    }
+  }
+}
+
+// k > 64 polish, one step over all slices: G (k x k, FP64, per slice) holds
+// X^T X on entry.  state: 0 polishing, 2 the step formed here is the last, 1
+// done (the later kernels of the step skip the slice).  Turns G into
+// M = 1.5 I - 0.5 G, or marks the slice done.
+template <typename T>
+__global__ __launch_bounds__(256) void ns_form_kernel(double* __restrict__ g, int n, int k,
+                                                      int* __restrict__ state) {
+  __shared__ double s_red[256];
+  const int slice = blockIdx.x;
+  const int st = state[slice];
+  if (st != 0) {
+    if (st == 2 && threadIdx.x == 0) state[slice] = 1;
+    return;
+  }
+  double* G = g + int64_t(slice) * k * k;
+  double t_done, t_last;
+  polish_thresholds<T>(n, t_done, t_last);
+  const double dev = gram_dev(G, k, s_red);
+  if (dev <= t_done) {
+    if (threadIdx.x == 0) state[slice] = 1;
+    return;
+  }
+  for (int64_t e = threadIdx.x; e < int64_t(k) * k; e += 256) {
+    const int64_t a = e / k, b = e - a * k;
+    G[e] = (a == b ? 1.5 : 0.0) - 0.5 * G[e];
+  }
+  if (threadIdx.x == 0 && !(dev > t_last)) state[slice] = 2;
+}
+
+// X <- Y for the slices still polishing (state != 1).
+template <typename T>
+__global__ __launch_bounds__(256) void ns_copy_kernel(const T* __restrict__ y, T* __restrict__ x,
+                                                      int64_t per, const int* __restrict__ state) {
+  const int slice = blockIdx.y;
+  if (state[slice] == 1) return;
+  const T* ys = y + slice * per;
+  T* xs = x + slice * per;
+  for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < per; e += int64_t(gridDim.x) * 256)
+    xs[e] = ys[e];
+}
+
+// Orthogonality of one slice from its Gram matrix in memory (k > 64).
+__global__ __launch_bounds__(256) void gram_dev_kernel(const double* __restrict__ g, int k,
+                                                       double* __restrict__ part) {
+  __shared__ double s_red[256];
+  const double dev = gram_dev(g + int64_t(blockIdx.x) * k * k, k, s_red);
+  if (threadIdx.x == 0) part[blockIdx.x] = dev;
+}
+
+// max |X^T X - I| over the k x k Gram matrix of one slice of X (n x k,
+// row-major, k <= 64), FP64, zero columns left out.
+template <typename T>
+__global__ __launch_bounds__(256) void orth_kernel(const T* __restrict__ x, int n, int k,
+                                                   double* __restrict__ part) {
+  __shared__ double s_g[64 * 64];
+  __shared__ double s_blk[kGramRows * 64];
+  __shared__ double s_red[256];
+  const int slice = blockIdx.x;
+  double acc[16];
+  gram_k64<T>(x + int64_t(slice) * n * k, n, k, acc, s_blk);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    if (e < k * k) s_g[e] = acc[q];
+  }
+  __syncthreads();
+  const double dev = gram_dev(s_g, k, s_red);
+  if (threadIdx.x == 0) part[slice] = dev;
 }
 
 __global__ __launch_bounds__(256) void max_reduce_kernel(const double* __restrict__ part, int64_t n,
@@ -1060,12 +1228,15 @@ inline JacobiChoice choose_jacobi(int mr, int nc, size_t es, int64_t nsl) {
 }
 
 struct SvdPlan {
-  size_t ah, w, us, ctl, part, total;
+  size_t ah, w, us, ctl, part, gram, y, state, total;
 };
 
 // p coefficient slices are lifted; the first nsl of them are decomposed
-// (nsl = p for w-svd, 2 p / 2^L for sp-w-svd).
-inline SvdPlan plan_svd(int64_t n1, int64_t n2, int64_t p, int64_t nsl, int k, size_t es) {
+// (nsl = p for w-svd, 2 p / 2^L for sp-w-svd).  With polish (w-svd, not the
+// pseudo-inverse) and k > 64 the plan also holds the FP64 Gram matrices and
+// the update buffer of the Newton-Schulz steps and of the orthogonality check.
+inline SvdPlan plan_svd(int64_t n1, int64_t n2, int64_t p, int64_t nsl, int k, size_t es,
+                        bool polish) {
   const int64_t mr = n1 > n2 ? n1 : n2;
   const int64_t nc = n1 > n2 ? n2 : n1;
   const JacobiChoice jc = choose_jacobi(int(mr), int(nc), es, nsl);
@@ -1082,6 +1253,10 @@ inline SvdPlan plan_svd(int64_t n1, int64_t n2, int64_t p, int64_t nsl, int k, s
   pl.us = take(size_t(nsl * n1 * k) * es);
   pl.ctl = take(size_t(nsl) * sizeof(BjCtl));
   pl.part = take(size_t(nsl) * 2 * sizeof(double));
+  const bool big = polish && k > 64;
+  pl.gram = take(big ? size_t(nsl) * k * k * sizeof(double) : 0);
+  pl.y = take(big ? size_t(nsl * (n1 > n2 ? n1 : n2)) * k * es : 0);
+  pl.state = take(size_t(nsl) * sizeof(int));
   pl.total = off + 256;
   return pl;
 }
@@ -1097,17 +1272,21 @@ __global__ __launch_bounds__(256) void zero_kernel(T* __restrict__ x, int64_t n)
 template <typename T>
 hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, bool sparse,
                    T* uhat, T* shat, T* vhat, T* ak, int max_sweeps, int32_t* info,
-                   double* orth_err, void* ws, hipStream_t s, bool second_factor = true) {
+                   double* orth_err, void* ws, hipStream_t s, bool second_factor = true,
+                   hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr) {
   // sp-w-svd decomposes only s_L and d_L, the leading 2 p / 2^L coefficient
   // slices; the finer details are dropped (zero) in the rebuild.
   const int64_t nsl = sparse ? 2 * (p >> L) : p;
-  const SvdPlan pl = plan_svd(n1, n2, p, nsl, k, sizeof(T));
+  const SvdPlan pl = plan_svd(n1, n2, p, nsl, k, sizeof(T), second_factor);
   char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
   T* ah = reinterpret_cast<T*>(base + pl.ah);
   T* w = reinterpret_cast<T*>(base + pl.w);
   T* us = reinterpret_cast<T*>(base + pl.us);
   BjCtl* ctl = reinterpret_cast<BjCtl*>(base + pl.ctl);
   double* part = reinterpret_cast<double*>(base + pl.part);
+  double* gram = reinterpret_cast<double*>(base + pl.gram);
+  T* ybuf = reinterpret_cast<T*>(base + pl.y);
+  int* state = reinterpret_cast<int*>(base + pl.state);
 
   hipError_t e;
   if constexpr (sizeof(T) == 8)
@@ -1130,6 +1309,10 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
   if (max_sweeps <= 0) max_sweeps = sizeof(T) == 8 ? 30 : 20;
 
   const JacobiChoice jc = choose_jacobi(d.mr, d.nc, sizeof(T), nsl);
+  if (ev_begin != nullptr) {
+    e = hipEventRecord(ev_begin, s);
+    if (e != hipSuccess) return e;
+  }
   if (jc.reg) {
     const dim3 grid{unsigned(nsl)};
     const dim3 block{unsigned(kJacobiThreads)};
@@ -1182,6 +1365,7 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
                        ncb, ctl, uhat, shat, vhat, us, info);
   }
   e = hipGetLastError();
+  if (e == hipSuccess && ev_end != nullptr) e = hipEventRecord(ev_end, s);
   if (e != hipSuccess || !second_factor) return e;
   hipLaunchKernelGGL((recover_kernel<T>), dim3(unsigned(nsl * k)), dim3(256), 0, s, ah, d, uhat,
                      shat, vhat, us);
@@ -1216,23 +1400,56 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
     if (e != hipSuccess) return e;
   }
 
-  if (k <= 64) {
+  {
     // Orthonormalise the recovered factor (after the rebuild, which uses the
     // recovered columns as they are: their product with U is the exact rank-k
     // projection U U^T A).
-    if (d.trans)
-      hipLaunchKernelGGL((polish_kernel<T>), dim3(unsigned(nsl)), dim3(256), 0, s, uhat, int(n1), k);
-    else
-      hipLaunchKernelGGL((polish_kernel<T>), dim3(unsigned(nsl)), dim3(256), 0, s, vhat, int(n2), k);
+    T* xr = d.trans ? uhat : vhat;
+    const int nr = int(d.trans ? n1 : n2);
+    if (k <= 64) {
+      hipLaunchKernelGGL((polish_kernel<T>), dim3(unsigned(nsl)), dim3(256), 0, s, xr, nr, k);
+    } else {
+      hipLaunchKernelGGL((zero_kernel<int>), dim3(unsigned((nsl + 255) / 256)), dim3(256), 0, s,
+                         state, nsl);
+      const unsigned kt = unsigned((k + 63) / 64);
+      const dim3 ggram{kt, kt, unsigned(nsl)};
+      const dim3 gapply{kt, unsigned((nr + 63) / 64), unsigned(nsl)};
+      const int64_t per = int64_t(nr) * k;
+      const int64_t cb = (per + 255) / 256;
+      const dim3 gcopy{unsigned(cb < 64 ? cb : 64), unsigned(nsl)};
+      for (int step = 0; step < kPolishSteps; ++step) {
+        hipLaunchKernelGGL((small_gemm_kernel<T, T, double, true>), ggram, dim3(256), 0, s, xr, xr,
+                           gram, k, nr, k, per, per, int64_t(k) * k, state);
+        hipLaunchKernelGGL((ns_form_kernel<T>), dim3(unsigned(nsl)), dim3(256), 0, s, gram, nr, k,
+                           state);
+        hipLaunchKernelGGL((small_gemm_kernel<T, double, T, false>), gapply, dim3(256), 0, s, xr,
+                           gram, ybuf, nr, k, k, per, int64_t(k) * k, per, state);
+        hipLaunchKernelGGL((ns_copy_kernel<T>), gcopy, dim3(256), 0, s, ybuf, xr, per, state);
+      }
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
 
   if (orth_err != nullptr) {
-    hipLaunchKernelGGL((orth_kernel<T>), dim3(unsigned(nsl)), dim3(256), 0, s, uhat, int(n1), k, part);
-    hipLaunchKernelGGL((orth_kernel<T>), dim3(unsigned(nsl)), dim3(256), 0, s, vhat, int(n2), k, part + nsl);
-    hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, s, part, nsl, orth_err);
-    hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, s, part + nsl, nsl, orth_err + 1);
+    const T* fac[2] = {uhat, vhat};
+    const int rows[2] = {int(n1), int(n2)};
+    for (int f = 0; f < 2; ++f) {
+      if (k <= 64) {
+        hipLaunchKernelGGL((orth_kernel<T>), dim3(unsigned(nsl)), dim3(256), 0, s, fac[f], rows[f],
+                           k, part + f * nsl);
+      } else {
+        const unsigned kt = unsigned((k + 63) / 64);
+        const int64_t per = int64_t(rows[f]) * k;
+        hipLaunchKernelGGL((small_gemm_kernel<T, T, double, true>), dim3(kt, kt, unsigned(nsl)),
+                           dim3(256), 0, s, fac[f], fac[f], gram, k, rows[f], k, per, per,
+                           int64_t(k) * k, static_cast<const int*>(nullptr));
+        hipLaunchKernelGGL(gram_dev_kernel, dim3(unsigned(nsl)), dim3(256), 0, s, gram, k,
+                           part + f * nsl);
+      }
+      hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, s, part + f * nsl, nsl,
+                         orth_err + f);
+    }
     e = hipGetLastError();
   }
   return e;
@@ -1272,7 +1489,7 @@ inline PinvPlan plan_pinv(int64_t n1, int64_t n2, int64_t p, int64_t nsl, size_t
     off = align_up(off + bytes, 256);
     return at;
   };
-  const SvdPlan sp = plan_svd(n1, n2, p, nsl, int(k), es);
+  const SvdPlan sp = plan_svd(n1, n2, p, nsl, int(k), es, false);
   pl.svd = take(sp.total);
   pl.uh = take(size_t(nsl * n1 * k) * es);
   pl.sh = take(size_t(nsl * k) * es);
@@ -1303,7 +1520,7 @@ hipError_t run_pinv(const T* a, T* out, int64_t n1, int64_t n2, int64_t p, int L
   T* ph = reinterpret_cast<T*>(base + pl.ph);
   // The coefficient slices, lifted by run_svd into its own workspace region.
   const T* ah = reinterpret_cast<const T*>(base + pl.svd +
-                                           plan_svd(n1, n2, p, nsl, int(k), sizeof(T)).ah);
+                                           plan_svd(n1, n2, p, nsl, int(k), sizeof(T), false).ah);
   hipError_t e = run_svd<T>(a, n1, n2, p, L, int(k), sparse, uh, sh, vh, static_cast<T*>(nullptr),
                             0, info, nullptr, base + pl.svd, s, /*second_factor=*/false);
   if (e != hipSuccess) return e;
@@ -1372,21 +1589,23 @@ hipError_t launch_pinv(const void* a, void* out, int64_t n1, int64_t n2, int64_t
 
 size_t svd_workspace_bytes(int64_t n1, int64_t n2, int64_t p, int L, int k, bool sparse,
                            int dtype) {
-  return plan_svd(n1, n2, p, sparse ? 2 * (p >> L) : p, k, dtype == 0 ? 8 : 4).total;
+  return plan_svd(n1, n2, p, sparse ? 2 * (p >> L) : p, k, dtype == 0 ? 8 : 4, true).total;
 }
 
 hipError_t launch_svd(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k, bool sparse,
                       void* uhat, void* shat, void* vhat, void* ak, int max_sweeps, int32_t* info,
-                      double* orth_err, int dtype, void* ws, hipStream_t s) {
+                      double* orth_err, int dtype, void* ws, hipStream_t s, hipEvent_t ev_begin,
+                      hipEvent_t ev_end) {
   if (dtype == 0)
     return run_svd<double>(static_cast<const double*>(a), n1, n2, p, L, k, sparse,
                            static_cast<double*>(uhat),
                            static_cast<double*>(shat), static_cast<double*>(vhat),
-                           static_cast<double*>(ak), max_sweeps, info, orth_err, ws, s);
+                           static_cast<double*>(ak), max_sweeps, info, orth_err, ws, s, true,
+                           ev_begin, ev_end);
   return run_svd<float>(static_cast<const float*>(a), n1, n2, p, L, k, sparse,
                         static_cast<float*>(uhat),
                         static_cast<float*>(shat), static_cast<float*>(vhat), static_cast<float*>(ak),
-                        max_sweeps, info, orth_err, ws, s);
+                        max_sweeps, info, orth_err, ws, s, true, ev_begin, ev_end);
 }
 
 }  // namespace wp

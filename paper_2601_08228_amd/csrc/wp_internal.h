@@ -63,9 +63,12 @@ hipError_t launch_face_bf16(const uint16_t* ahi, const uint16_t* alo, const uint
 // 2 p / 2^L slices.
 size_t svd_workspace_bytes(int64_t n1, int64_t n2, int64_t p, int L, int k, bool sparse,
                            int dtype);
+// ev_begin / ev_end (may be null) are recorded on s just before and just after
+// the Jacobi stage.
 hipError_t launch_svd(const void* a, int64_t n1, int64_t n2, int64_t p, int L, int k,
                       bool sparse, void* uhat, void* shat, void* vhat, void* ak, int max_sweeps,
-                      int32_t* info, double* orth_err, int dtype, void* ws, hipStream_t s);
+                      int32_t* info, double* orth_err, int dtype, void* ws, hipStream_t s,
+                      hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
 
 // Moore-Penrose inverse (Def. 2.6) through the same SVD; out is (p, n2, n1).
 size_t pinv_workspace_bytes(int64_t n1, int64_t n2, int64_t p, int L, bool sparse, int dtype);

@@ -19,8 +19,9 @@ from . import _lib
 __all__ = [
     "w_transform", "w_itransform", "w_transform_adj", "w_itransform_adj",
     "w_transform_split", "w_itransform_adj_split", "w_face_product",
-    "w_face_product_split", "w_product", "w_product_workspace", "w_svd",
-    "w_svd_workspace", "w_svd_sparse", "w_svd_sparse_workspace", "SvdResult", "w_pinv",
+    "w_face_product_split", "w_face_product_gemm", "w_face_product_workspace", "w_product",
+    "w_product_workspace", "w_svd", "w_svd_timed", "w_svd_workspace", "w_svd_sparse",
+    "w_svd_sparse_workspace", "SvdResult", "w_pinv",
     "w_pinv_workspace", "SCHEME_KINDS", "w_transform_scheme", "w_transform_scheme_split",
     "w_product_scheme", "w_product_scheme_workspace",
 ]
@@ -50,14 +51,45 @@ def _dev_tensor(t, name, dtypes):
     return t
 
 
+def _out_tensor(out, name, shape, dtype, device):
+    """Check a caller-supplied output: device tensor on `device`, dtype, shape, contiguous."""
+    if not isinstance(out, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if out.device != device:
+        raise ValueError("%s is on %s; expected %s" % (name, out.device, device))
+    if out.dtype != dtype:
+        raise ValueError("%s has dtype %s; expected %s" % (name, out.dtype, dtype))
+    if tuple(out.shape) != tuple(shape):
+        raise ValueError("%s has shape %s; expected %s" % (name, tuple(out.shape), tuple(shape)))
+    if not out.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return out
+
+
+def _workspace(ws, need, device):
+    """Allocate the workspace, or check a caller-supplied one (contiguous, on
+    `device`, at least `need` bytes); returns (tensor, size in bytes)."""
+    if ws is None:
+        ws = torch.empty(max(int(need), 1), dtype=torch.uint8, device=device)
+    else:
+        if not isinstance(ws, torch.Tensor):
+            raise TypeError("workspace must be a torch.Tensor")
+        if ws.device != device:
+            raise ValueError("workspace is on %s; expected %s" % (ws.device, device))
+        if not ws.is_contiguous():
+            raise ValueError("workspace must be contiguous")
+        if ws.numel() * ws.element_size() < need:
+            raise ValueError("workspace holds %d bytes; %d needed"
+                             % (ws.numel() * ws.element_size(), need))
+    return ws, ws.numel() * ws.element_size()
+
+
 def _lift(fn_name, x, L, out):
     _dev_tensor(x, "x", tuple(_DT))
     if out is None:
         out = torch.empty_like(x)
     else:
-        _dev_tensor(out, "out", (x.dtype,))
-        if out.shape != x.shape:
-            raise ValueError("out has the wrong shape")
+        _out_tensor(out, "out", x.shape, x.dtype, x.device)
     p, n1, n2 = x.shape
     with torch.cuda.device(x.device):
         st = getattr(_lib.load(), fn_name)(_ptr(x), _ptr(out), n1, n2, p, int(L), _DT[x.dtype],
@@ -126,9 +158,7 @@ def w_face_product(ah, bh, trans_a=False, trans_b=False, out=None):
     if out is None:
         out = torch.empty((p, n1, n3), dtype=ah.dtype, device=ah.device)
     else:
-        _dev_tensor(out, "out", (ah.dtype,))
-        if tuple(out.shape) != (p, n1, n3):
-            raise ValueError("out has the wrong shape")
+        _out_tensor(out, "out", (p, n1, n3), ah.dtype, ah.device)
     with torch.cuda.device(ah.device):
         st = _lib.load().w_face_product(_ptr(ah), _ptr(bh), _ptr(out), n1, n2, n3, p, int(trans_a),
                                         int(trans_b), _DT[ah.dtype], _stream(ah))
@@ -150,17 +180,48 @@ def w_face_product_split(a_hi, a_lo, b_hi, b_lo, trans_a=False, trans_b=False, g
     else:
         a_lo = b_lo = None
     p, n1, n2, n3 = _face_dims(a_hi, b_hi, trans_a, trans_b)
+    for t, name in ((a_lo, "a_lo"), (b_hi, "b_hi"), (b_lo, "b_lo")):
+        if t is not None and t.device != a_hi.device:
+            raise ValueError("%s is on %s; expected %s" % (name, t.device, a_hi.device))
     if out is None:
         out = torch.empty((p, n1, n3), dtype=torch.float32, device=a_hi.device)
     else:
-        _dev_tensor(out, "out", (torch.float32,))
-        if tuple(out.shape) != (p, n1, n3):
-            raise ValueError("out has the wrong shape")
+        _out_tensor(out, "out", (p, n1, n3), torch.float32, a_hi.device)
     with torch.cuda.device(a_hi.device):
         st = _lib.load().w_face_product_split(_ptr(a_hi), _ptr(a_lo), _ptr(b_hi), _ptr(b_lo),
                                               _ptr(out), n1, n2, n3, p, int(trans_a),
                                               int(trans_b), mode, _stream(a_hi))
     _lib.check("w_face_product_split", st)
+    return out
+
+
+def w_face_product_workspace(n1, n2, n3, p, dtype=torch.float32, gemm="native"):
+    return int(_lib.load().w_face_product_workspace(n1, n2, n3, p, _DT[dtype],
+                                                    _lib.GEMM_MODES[gemm]))
+
+
+def w_face_product_gemm(ah, bh, trans_a=False, trans_b=False, gemm="native", out=None,
+                        workspace=None):
+    """Face-product (Def. 2.1) in one call for every arithmetic: 'native' (FP64 /
+    FP32 MFMA), or 'bf16' / 'bf16x3' of float32 coefficients, split into bf16
+    hi / lo planes inside the call."""
+    _dev_tensor(ah, "ah", tuple(_DT))
+    _dev_tensor(bh, "bh", (ah.dtype,))
+    if bh.device != ah.device:
+        raise ValueError("bh is on %s; expected %s" % (bh.device, ah.device))
+    p, n1, n2, n3 = _face_dims(ah, bh, trans_a, trans_b)
+    mode = _lib.GEMM_MODES[gemm]
+    if out is None:
+        out = torch.empty((p, n1, n3), dtype=ah.dtype, device=ah.device)
+    else:
+        _out_tensor(out, "out", (p, n1, n3), ah.dtype, ah.device)
+    need = w_face_product_workspace(n1, n2, n3, p, ah.dtype, gemm) if ah.dtype in _DT else 0
+    workspace, nbytes = _workspace(workspace, need, ah.device)
+    with torch.cuda.device(ah.device):
+        st = _lib.load().w_face_product_gemm(_ptr(ah), _ptr(bh), _ptr(out), n1, n2, n3, p,
+                                             int(trans_a), int(trans_b), _DT[ah.dtype], mode,
+                                             _ptr(workspace), nbytes, _stream(ah))
+    _lib.check("w_face_product_gemm", st)
     return out
 
 
@@ -173,17 +234,20 @@ def w_product(a, b, L, trans_a=False, trans_b=False, gemm="native", out=None, wo
     """w-product C = op(A) *_w op(B) (Def. 2.1, Alg. 1) in one library call."""
     _dev_tensor(a, "a", tuple(_DT))
     _dev_tensor(b, "b", (a.dtype,))
+    if b.device != a.device:
+        raise ValueError("b is on %s; expected %s" % (b.device, a.device))
     p, n1, n2, n3 = _face_dims(a, b, trans_a, trans_b)
     mode = _lib.GEMM_MODES[gemm]
     need = w_product_workspace(n1, n2, n3, p, L, a.dtype, gemm)
-    if workspace is None:
-        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=a.device)
+    workspace, nbytes = _workspace(workspace, need, a.device)
     if out is None:
         out = torch.empty((p, n1, n3), dtype=a.dtype, device=a.device)
+    else:
+        _out_tensor(out, "out", (p, n1, n3), a.dtype, a.device)
     with torch.cuda.device(a.device):
         st = _lib.load().w_product(_ptr(a), _ptr(b), _ptr(out), n1, n2, n3, p, int(L), int(trans_a),
-                                   int(trans_b), _DT[a.dtype], mode, _ptr(workspace),
-                                   workspace.numel() * workspace.element_size(), _stream(a))
+                                   int(trans_b), _DT[a.dtype], mode, _ptr(workspace), nbytes,
+                                   _stream(a))
     _lib.check("w_product", st)
     return out
 
@@ -199,7 +263,7 @@ def w_svd_sparse_workspace(n1, n2, p, L, k, dtype=torch.float32):
     return int(_lib.load().w_svd_sparse_workspace(n1, n2, p, int(L), int(k), _DT[dtype]))
 
 
-def _svd_call(name, a, L, k, nsl, max_sweeps, want_ak, want_orth, workspace):
+def _svd_call(name, a, L, k, nsl, max_sweeps, want_ak, want_orth, workspace, events=()):
     _dev_tensor(a, "a", tuple(_DT))
     p, n1, n2 = a.shape
     k = int(k)
@@ -212,14 +276,13 @@ def _svd_call(name, a, L, k, nsl, max_sweeps, want_ak, want_orth, workspace):
     info = torch.empty((nsl,), dtype=torch.int32, device=dev)
     orth = torch.empty((2,), dtype=torch.float64, device=dev) if want_orth else None
     lib = _lib.load()
-    need = getattr(lib, name + "_workspace")(n1, n2, p, int(L), k, _DT[a.dtype])
-    if workspace is None:
-        workspace = torch.empty(max(int(need), 1), dtype=torch.uint8, device=dev)
+    ws_name = name[:-len("_timed")] if name.endswith("_timed") else name
+    need = getattr(lib, ws_name + "_workspace")(n1, n2, p, int(L), k, _DT[a.dtype])
+    workspace, nbytes = _workspace(workspace, need, dev)
     with torch.cuda.device(dev):
         st = getattr(lib, name)(_ptr(a), n1, n2, p, int(L), k, _ptr(uhat), _ptr(shat), _ptr(vhat),
                                 _ptr(ak), int(max_sweeps), _ptr(info), _ptr(orth), _DT[a.dtype],
-                                _ptr(workspace), workspace.numel() * workspace.element_size(),
-                                _stream(a))
+                                _ptr(workspace), nbytes, _stream(a), *events)
     _lib.check(name, st)
     return SvdResult(uhat, shat, vhat, ak, info, orth)
 
@@ -233,6 +296,23 @@ def w_svd(a, L, k, max_sweeps=0, want_ak=True, want_orth=True, workspace=None):
     """
     p = a.shape[0] if a.dim() == 3 else 0
     return _svd_call("w_svd", a, L, k, p, max_sweeps, want_ak, want_orth, workspace)
+
+
+def w_svd_timed(a, L, k, jacobi_begin, jacobi_end, max_sweeps=0, want_ak=True, want_orth=True,
+                workspace=None):
+    """w_svd with two torch.cuda.Event objects (created with enable_timing=True)
+    recorded on the current stream just before and after the Jacobi stage, so
+    that jacobi_begin.elapsed_time(jacobi_end) times the decomposition alone."""
+    evs = []
+    for ev, name in ((jacobi_begin, "jacobi_begin"), (jacobi_end, "jacobi_end")):
+        if not isinstance(ev, torch.cuda.Event):
+            raise TypeError("%s must be a torch.cuda.Event" % name)
+        if not ev.cuda_event:
+            ev.record()  # torch creates the HIP event on its first record
+        evs.append(ctypes.c_void_p(ev.cuda_event))
+    p = a.shape[0] if a.dim() == 3 else 0
+    return _svd_call("w_svd_timed", a, L, k, p, max_sweeps, want_ak, want_orth, workspace,
+                     tuple(evs))
 
 
 def w_svd_sparse(a, L, k, max_sweeps=0, want_ak=True, want_orth=True, workspace=None):
@@ -265,12 +345,10 @@ def w_pinv(a, L, sparse=False, rtol=0.0, workspace=None):
     info = torch.empty((max(nsl, 0),), dtype=torch.int32, device=a.device)
     lib = _lib.load()
     need = lib.w_pinv_workspace(n1, n2, p, int(L), int(bool(sparse)), _DT[a.dtype])
-    if workspace is None:
-        workspace = torch.empty(max(int(need), 1), dtype=torch.uint8, device=a.device)
+    workspace, nbytes = _workspace(workspace, need, a.device)
     with torch.cuda.device(a.device):
         st = lib.w_pinv(_ptr(a), _ptr(out), n1, n2, p, int(L), int(bool(sparse)), float(rtol),
-                        _ptr(info), _DT[a.dtype], _ptr(workspace),
-                        workspace.numel() * workspace.element_size(), _stream(a))
+                        _ptr(info), _DT[a.dtype], _ptr(workspace), nbytes, _stream(a))
     _lib.check("w_pinv", st)
     return out, info
 
@@ -296,9 +374,7 @@ def w_transform_scheme(x, L, taps, kind="forward", out=None):
     if out is None:
         out = torch.empty_like(x)
     else:
-        _dev_tensor(out, "out", (x.dtype,))
-        if out.shape != x.shape:
-            raise ValueError("out has the wrong shape")
+        _out_tensor(out, "out", x.shape, x.dtype, x.device)
     p, n1, n2 = x.shape
     with torch.cuda.device(x.device):
         st = _lib.load().w_transform_scheme(_ptr(x), _ptr(out), n1, n2, p, int(L),
@@ -332,19 +408,21 @@ def w_product_scheme(a, b, L, taps, trans_a=False, trans_b=False, gemm="native",
     """w-product (Def. 2.1) under the lifting with stencils taps (L, 2, 5)."""
     _dev_tensor(a, "a", tuple(_DT))
     _dev_tensor(b, "b", (a.dtype,))
+    if b.device != a.device:
+        raise ValueError("b is on %s; expected %s" % (b.device, a.device))
     t = _taps(taps, L)
     p, n1, n2, n3 = _face_dims(a, b, trans_a, trans_b)
     mode = _lib.GEMM_MODES[gemm]
     need = w_product_scheme_workspace(n1, n2, n3, p, L, a.dtype, gemm)
-    if workspace is None:
-        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=a.device)
+    workspace, nbytes = _workspace(workspace, need, a.device)
     if out is None:
         out = torch.empty((p, n1, n3), dtype=a.dtype, device=a.device)
+    else:
+        _out_tensor(out, "out", (p, n1, n3), a.dtype, a.device)
     with torch.cuda.device(a.device):
         st = _lib.load().w_product_scheme(_ptr(a), _ptr(b), _ptr(out), n1, n2, n3, p, int(L),
                                           t.ctypes.data, int(trans_a), int(trans_b),
-                                          _DT[a.dtype], mode, _ptr(workspace),
-                                          workspace.numel() * workspace.element_size(),
+                                          _DT[a.dtype], mode, _ptr(workspace), nbytes,
                                           _stream(a))
     _lib.check("w_product_scheme", st)
     return out

@@ -128,3 +128,58 @@ def test_graphed_solve_matches_eager_every_replay(wp, gemm):
         torch.cuda.synchronize()
         assert torch.equal(solver.x.detach(), xe), step
     assert solver.residual_norm2() < loss0
+
+
+@pytest.mark.parametrize("gemm", ["native", "bf16x3"])
+def test_full_size_backward_512x512x256_sampled(wp, gemm):
+    # The benchmark's forward + backward (A, B 512x512x256 N(0,1), L = 4,
+    # cotangent N(0,1)): sampled rows of dA = G *_w B^T and sampled columns of
+    # dB = A^T *_w G against the oracle's derivative restricted to those rows /
+    # columns (a row of dA needs only that row of G, a column of dB only that
+    # column of G).
+    import torch
+    from paper_2601_08228_amd import synth
+    dev = device()
+    a = synth.normal_device((256, 512, 512), 21, dev)
+    b = synth.normal_device((256, 512, 512), 22, dev)
+    g = synth.normal_device((256, 512, 512), 102, dev)
+    ta = a.clone().requires_grad_(True)
+    tb = b.clone().requires_grad_(True)
+    wp.w_product_ad(ta, tb, 4, gemm).backward(g)
+    torch.cuda.synchronize()
+    a_h, b_h, g_h = (host(t).astype(np.float64) for t in (a, b, g))
+    da, db = host(ta.grad).astype(np.float64), host(tb.grad).astype(np.float64)
+    rng = np.random.default_rng(8)
+    got, ref = [], []
+    for i in rng.integers(0, 512, 4):
+        da_i, _ = orc.w_product_vjp(a_h[:, i:i + 1, :], b_h, g_h[:, i:i + 1, :], 4)
+        got.append(da[:, i, :])
+        ref.append(da_i[:, 0, :])
+    assert rel_fro(np.array(got), np.array(ref)) <= 1e-5
+    got, ref = [], []
+    for j in rng.integers(0, 512, 4):
+        _, db_j = orc.w_product_vjp(a_h, b_h[:, :, j:j + 1], g_h[:, :, j:j + 1], 4)
+        got.append(db[:, :, j])
+        ref.append(db_j[:, :, 0])
+    assert rel_fro(np.array(got), np.array(ref)) <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def deblur_full():
+    # The deblurring workload at its stated size (256x256x128, L = 3) and the
+    # oracle's 50-step trajectory, computed once for both face-product modes.
+    k, x, y, eta = _deblur_problem(256, 128, seed=5)
+    x_ref, loss_ref = orc.deblur_gd(k, y, 3, 50, eta)
+    return k, y, eta, x_ref, loss_ref
+
+
+@pytest.mark.parametrize("gemm", ["native", "bf16x3"])
+def test_deblur_trajectory_full_size(wp, deblur_full, gemm):
+    import torch
+    from paper_2601_08228_amd import deblur
+    k, y, eta, x_ref, loss_ref = deblur_full
+    xs, losses = deblur.solve(to_dev(k, torch.float32), to_dev(y, torch.float32), 3, steps=50,
+                              eta=eta, gemm=gemm)
+    assert rel_fro(host(xs), x_ref) <= 1e-5
+    np.testing.assert_allclose(losses, loss_ref[:len(losses)], rtol=1e-4)
+    assert losses[-1] < losses[0]

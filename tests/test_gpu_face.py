@@ -131,3 +131,42 @@ def test_unaligned_pitch_uses_scalar_loads(wp):
     a, b = _operands(6, 45, 3, 37, False, False, seed=2)
     out = host(wp.w_face_product(to_dev(a, torch.float64), to_dev(b, torch.float64)))
     assert rel_fro(out, orc.face(a, b)) <= 1e-15
+
+
+# The single-call form with the GEMM mode and a workspace: native equals
+# w_face_product bit for bit; the BF16 modes split the FP32 operands inside
+# the call and match the split face-product of the same planes bit for bit,
+# and the oracle within the mode's error.
+@pytest.mark.parametrize("shape", [(3, 130, 70, 200), (2, 264, 200, 328), (4, 9, 5, 3)])
+@pytest.mark.parametrize("tt", TRANS)
+def test_gemm_single_call(wp, shape, tt):
+    import torch
+    p, m, k, n = shape
+    a, b = _operands(p, m, k, n, *tt, seed=m + 5 * n)
+    a, b = cast(a, np.float32), cast(b, np.float32)
+    ta_, tb_ = to_dev(a, torch.float32), to_dev(b, torch.float32)
+    ref = orc.face(a, b, *tt)
+    nat = wp.w_face_product_gemm(ta_, tb_, *tt, gemm="native")
+    assert torch.equal(nat, wp.w_face_product(ta_, tb_, *tt))
+    for gemm, tol in (("bf16x3", 1e-5), ("bf16", 2e-2)):
+        got = wp.w_face_product_gemm(ta_, tb_, *tt, gemm=gemm)
+        hi_a, lo_a = wp.w_transform_split(ta_, 0)
+        hi_b, lo_b = wp.w_transform_split(tb_, 0)
+        split = wp.w_face_product_split(hi_a, lo_a, hi_b, lo_b, *tt, gemm=gemm)
+        assert torch.equal(got, split), gemm
+        assert rel_fro(host(got), ref) <= tol, gemm
+
+
+def test_gemm_single_call_workspace_checks(wp):
+    import torch
+    from paper_2601_08228_amd._lib import WprodError
+    a = to_dev(np.ones((2, 8, 8)), torch.float32)
+    need = wp.w_face_product_workspace(8, 8, 8, 2, torch.float32, "bf16x3")
+    assert need > 0 and wp.w_face_product_workspace(8, 8, 8, 2, torch.float32, "native") == 0
+    with pytest.raises(ValueError):
+        wp.w_face_product_gemm(a, a, gemm="bf16x3",
+                               workspace=torch.empty(need - 1, dtype=torch.uint8, device=a.device))
+    # BF16 modes need FP32 data (WP_EDTYPE from the library, nothing launched).
+    d = to_dev(np.ones((2, 8, 8)), torch.float64)
+    with pytest.raises(WprodError):
+        wp.w_face_product_gemm(d, d, gemm="bf16x3")

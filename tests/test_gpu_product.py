@@ -129,3 +129,24 @@ def test_full_size_1024x1024x128_sampled(wp, gemm, tol):
     torch.cuda.synchronize()
     got, ref = _sampled_tubes(a, b, c, 3, 64, seed=2)
     assert rel_fro(got, ref) <= tol
+
+
+# Table 1 shapes (Sec. III): A, B p x p x p with U[0,1) entries and L = log2 p,
+# the largest two rows of the table, in the launch configuration the Table 1
+# benchmark times; 32 sampled tubes against the oracle.
+@pytest.mark.parametrize("gemm", ["native", "bf16x3"])
+@pytest.mark.parametrize("e", [9, 10])
+def test_table1_shapes_sampled(wp, gemm, e):
+    import torch
+    dev = device()
+    p = 1 << e
+    g = torch.Generator(device=dev)
+    g.manual_seed(1000 + e)
+    a = torch.rand((p, p, p), generator=g, device=dev)
+    b = torch.rand((p, p, p), generator=g, device=dev)
+    c = wp.w_product(a, b, e, gemm=gemm)
+    torch.cuda.synchronize()
+    got, ref = _sampled_tubes(a, b, c, e, 32, seed=e)
+    del a, b, c
+    torch.cuda.empty_cache()
+    assert rel_fro(got, ref) <= 1e-5

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import oracle as orc
-from gpu_helpers import device, to_dev, host, cast, rel_fro
+from gpu_helpers import device, to_dev, host, cast, rel_fro, svd_bars, UNIT
 
 pytestmark = pytest.mark.gpu
 
@@ -16,15 +16,18 @@ def wp():
     return wp
 
 
-def _check_factors(res, a_coeff, k, tol):
-    """uhat diag(shat) vhat^T against the oracle's rank-k rebuild, slice by slice."""
+def _check_factors(res, a_coeff, k, bars, prec="f64"):
+    """uhat diag(shat) vhat^T against the oracle's rank-k rebuild, slice by slice,
+    each slice within its own derived rank-k bar; every sigma within the Weyl
+    bar 4 mr u sigma_1 of its slice."""
     uh, sh, vh = host(res.uhat), host(res.shat), host(res.vhat)
+    mr = max(a_coeff.shape[1:])
     for c in range(a_coeff.shape[0]):
         u, s, v = orc.slice_svd(a_coeff[c])
-        np.testing.assert_allclose(sh[c], s[:k], rtol=tol, atol=tol * s[0])
+        np.testing.assert_allclose(sh[c], s[:k], rtol=0, atol=4 * mr * UNIT[prec] * s[0])
         rebuilt = (uh[c] * sh[c]) @ vh[c].T
         ref = (u[:, :k] * s[:k]) @ v[:, :k].T
-        assert rel_fro(rebuilt, ref) <= tol * 10
+        assert rel_fro(rebuilt, ref) <= bars["ak_slice"][c], (c, rel_fro(rebuilt, ref))
 
 
 def test_config1_f64_full_rank(wp):
@@ -36,16 +39,20 @@ def test_config1_f64_full_rank(wp):
     torch.cuda.synchronize()
     info = host(res.info)
     assert info.min() > 0
+    coeff = orc.lift_fwd(a, 2)
+    bars = svd_bars(coeff, 24, "f64", L=2)
+    assert bars["ak"] == 1e-12 and bars["shat"] == 1e-12
     assert rel_fro(host(res.ak), a) <= 1e-12
     _, sh_ref, _, _ = orc.w_svd(a, 2, 24)
-    assert rel_fro(host(res.shat), sh_ref) <= 1e-13
-    assert host(res.orth_err).max() <= 1e-13
-    _check_factors(res, orc.lift_fwd(a, 2), 24, 1e-12)
+    assert rel_fro(host(res.shat), sh_ref) <= bars["shat"]
+    assert host(res.orth_err).max() <= bars["orth"]
+    _check_factors(res, coeff, 24, bars)
 
 
 # Register-resident kernel: both orientations (n1 < n2 runs on the transpose),
 # odd column counts (a zero tournament column), 1 and 2 columns, rows spanning
-# several lanes.  General kernel: more than 256 rows.
+# several lanes.  Block kernel: more than 128 rows (FP64).  Every bar is
+# derived from the oracle's singular values of the coefficient slices.
 @pytest.mark.parametrize("shape,k", [((8, 10, 20), 5), ((16, 21, 13), 7), ((4, 9, 9), 9),
                                      ((8, 65, 40), 3), ((2, 3, 70), 1), ((32, 7, 7), 4),
                                      ((4, 5, 1), 1), ((4, 2, 6), 2), ((8, 130, 100), 10),
@@ -59,10 +66,12 @@ def test_f64_shapes(wp, shape, k):
     torch.cuda.synchronize()
     assert host(res.info).min() > 0
     _, sh_ref, _, ak_ref = orc.w_svd(a, L, k)
-    assert rel_fro(host(res.shat), sh_ref) <= 1e-12
-    assert rel_fro(host(res.ak), ak_ref) <= 1e-10
-    assert host(res.orth_err).max() <= 1e-13
-    _check_factors(res, orc.lift_fwd(a, L), k, 1e-10)
+    coeff = orc.lift_fwd(a, L)
+    bars = svd_bars(coeff, k, "f64", L=L)
+    assert rel_fro(host(res.shat), sh_ref) <= bars["shat"]
+    assert rel_fro(host(res.ak), ak_ref) <= bars["ak"]
+    assert host(res.orth_err).max() <= bars["orth"]
+    _check_factors(res, coeff, k, bars)
     # sign convention: largest-magnitude entry of every U column is positive
     uh = host(res.uhat)
     idx = np.argmax(np.abs(uh), axis=1)
@@ -80,10 +89,12 @@ def test_config3_hsi_f32(wp):
     assert info.min() > 0, info
     _, sh_ref, _, ak_ref = orc.w_svd(x, 3, 20)
     ak = host(res.ak)
+    # The stated target of this workload (1e-5) is held directly; the derived
+    # orthogonality bar applies to both factors.
     assert rel_fro(host(res.shat), sh_ref) <= 1e-5
     assert rel_fro(ak, ak_ref) <= 1e-5
     assert abs(orc.psnr(x, ak) - orc.psnr(x, ak_ref)) <= 0.01
-    assert host(res.orth_err).max() <= 1e-4
+    assert host(res.orth_err).max() <= svd_bars(orc.lift_fwd(x, 3)[:2], 20, "f32")["orth"]
 
 
 def test_nonconvergence_is_reported(wp):
@@ -146,6 +157,8 @@ def test_block_kernel_zero_slices(wp):
 @pytest.mark.parametrize("shape,k", [((16, 100, 60), 10), ((8, 33, 64), 8), ((4, 256, 256), 20),
                                      ((4, 600, 300), 20), ((4, 1200, 90), 12)])
 def test_f32_shapes(wp, shape, k):
+    # (4, 600, 300): the recovered factor has 300 rows, (4, 1200, 90) 90 rows
+    # of a 1200-row slice; both are polished like any other.
     import torch
     p, n1, n2 = shape
     L = 2
@@ -154,11 +167,86 @@ def test_f32_shapes(wp, shape, k):
     torch.cuda.synchronize()
     assert host(res.info).min() > 0
     _, sh_ref, _, ak_ref = orc.w_svd(a, L, k)
+    coeff = orc.lift_fwd(a, L)
+    bars = svd_bars(coeff, k, "f32", L=L)
+    assert rel_fro(host(res.shat), sh_ref) <= bars["shat"]
+    assert rel_fro(host(res.ak), ak_ref) <= bars["ak"]
+    assert host(res.orth_err).max() <= bars["orth"]
+    _check_factors(res, coeff, k, bars, "f32")
+
+
+def _gapped(p, n1, n2, k, seed, lead=10.0):
+    """Slices with a prescribed spectrum: k values in [lead/2, lead], the rest in
+    [0.05, 0.5], random orthogonal factors (test input, built with numpy QR)."""
+    rng = np.random.default_rng(seed)
+    nc = min(n1, n2)
+    out = np.empty((p, n1, n2))
+    for c in range(p):
+        q1, _ = np.linalg.qr(rng.standard_normal((n1, nc)))
+        q2, _ = np.linalg.qr(rng.standard_normal((n2, nc)))
+        s = np.concatenate([rng.uniform(lead / 2, lead, k), rng.uniform(0.05, 0.5, nc - k)])
+        out[c] = (q1 * np.sort(s)[::-1]) @ q2.T
+    return out
+
+
+# High rank (k > 64): the recovered factor is orthonormalised by the FP64
+# Newton-Schulz steps on workspace Gram matrices; full rank reproduces A.
+@pytest.mark.parametrize("k", [100, 256])
+def test_f32_high_rank_gaussian(wp, k):
+    import torch
+    a = cast(np.random.default_rng(256 + k).standard_normal((16, 256, 256)), np.float32)
+    res = wp.w_svd(to_dev(a, torch.float32), 2, k)
+    torch.cuda.synchronize()
+    assert host(res.info).min() > 0
+    _, sh_ref, _, ak_ref = orc.w_svd(a, 2, k)
+    coeff = orc.lift_fwd(a, 2)
+    bars = svd_bars(coeff, k, "f32", L=2)
+    assert rel_fro(host(res.shat), sh_ref) <= bars["shat"]
+    assert rel_fro(host(res.ak), ak_ref) <= bars["ak"]
+    if k == 256:
+        assert rel_fro(host(res.ak), a) <= 1e-5
+    assert host(res.orth_err).max() <= bars["orth"]
+
+
+def test_f32_high_rank_gapped(wp):
+    # A clear gap after sigma_100 (sigma_1 / gap <= 2.2).  At
+    # L = 0 (no lifting) the coefficient slices are the slices themselves, so
+    # the prescribed spectrum is the one decomposed.
+    import torch
+    k = 100
+    a = cast(_gapped(16, 256, 200, k, seed=11), np.float32)
+    res = wp.w_svd(to_dev(a, torch.float32), 0, k)
+    torch.cuda.synchronize()
+    assert host(res.info).min() > 0
+    _, sh_ref, _, ak_ref = orc.w_svd(a, 0, k)
+    bars = svd_bars(a, k, "f32", L=0)
+    # Held at the stated FP32 target, below the derived bar (which is at
+    # least 4 mr u = 6e-5 for 256 rows).
     assert rel_fro(host(res.shat), sh_ref) <= 1e-5
-    # Gaussian slices have well separated leading singular values: the rank-k
-    # approximation is determined to about the FP32 rounding of the data.
-    assert rel_fro(host(res.ak), ak_ref) <= 1e-4
-    assert host(res.orth_err).max() <= 1e-4
+    assert rel_fro(host(res.ak), ak_ref) <= 1e-5
+    assert host(res.orth_err).max() <= bars["orth"]
+    _check_factors(res, a, k, bars, "f32")
+
+
+@pytest.mark.parametrize("shape,k", [((4, 300, 200), 20), ((8, 100, 90), 90), ((4, 90, 140), 70)])
+def test_f64_long_and_high_rank(wp, shape, k):
+    # FP64: a 200-row recovered factor (block kernel), full rank 90 and rank 70
+    # of a transposed slice (the recovered factor is U) through the k > 64 polish.
+    import torch
+    p, n1, n2 = shape
+    a = np.random.default_rng(n1 * 7 + n2).standard_normal(shape)
+    res = wp.w_svd(to_dev(a, torch.float64), 2, k)
+    torch.cuda.synchronize()
+    assert host(res.info).min() > 0
+    _, sh_ref, _, ak_ref = orc.w_svd(a, 2, k)
+    coeff = orc.lift_fwd(a, 2)
+    bars = svd_bars(coeff, k, "f64", L=2)
+    assert rel_fro(host(res.shat), sh_ref) <= bars["shat"]
+    assert rel_fro(host(res.ak), ak_ref) <= bars["ak"]
+    if k == min(n1, n2):
+        assert rel_fro(host(res.ak), a) <= 1e-12
+    assert host(res.orth_err).max() <= bars["orth"]
+    _check_factors(res, coeff, k, bars)
 
 
 # Register kernel with 64 or more slices of untransposed columns: the columns
@@ -179,13 +267,10 @@ def test_register_kernel_staged_columns(wp, shape, dtype, k):
     torch.cuda.synchronize()
     assert host(res.info).min() > 0
     _, sh_ref, _, ak_ref = orc.w_svd(a, L, k)
-    if dtype == "f64":
-        assert rel_fro(host(res.shat), sh_ref) <= 1e-12
-        assert rel_fro(host(res.ak), ak_ref) <= 1e-12
-    else:
-        assert rel_fro(host(res.shat), sh_ref) <= 1e-5
-        assert rel_fro(host(res.ak), ak_ref) <= 1e-4
-        assert host(res.orth_err).max() <= 1e-4
+    bars = svd_bars(orc.lift_fwd(a, L), k, dtype, L=L)
+    assert rel_fro(host(res.shat), sh_ref) <= bars["shat"]
+    assert rel_fro(host(res.ak), ak_ref) <= bars["ak"]
+    assert host(res.orth_err).max() <= bars["orth"]
 
 
 # ---- sp-w-svd (Sec. IV-B): only s_L and d_L are decomposed ---------------------
@@ -203,11 +288,13 @@ def test_sparse_f64_shapes(wp, shape, L, k):
     assert res.uhat.shape == (nk, n1, k) and res.shat.shape == (nk, k)
     assert host(res.info).min() > 0
     uh_ref, sh_ref, vh_ref, ak_ref = orc.w_svd_sparse(a, L, k)
-    assert rel_fro(host(res.shat), sh_ref) <= 1e-12
+    coeff = orc.lift_fwd(a, L)[:nk]
+    bars = svd_bars(coeff, k, "f64", L=L, p=p)
+    assert rel_fro(host(res.shat), sh_ref) <= bars["shat"]
     ak = host(res.ak)
-    assert rel_fro(ak, ak_ref) <= 1e-10
-    assert host(res.orth_err).max() <= 1e-13
-    _check_factors(res, orc.lift_fwd(a, L)[:nk], k, 1e-10)
+    assert rel_fro(ak, ak_ref) <= bars["ak"]
+    assert host(res.orth_err).max() <= bars["orth"]
+    _check_factors(res, coeff, k, bars)
     # the finer details of the rebuilt tensor are absent (up to rounding)
     if nk < p:
         assert np.abs(orc.lift_fwd(ak, L)[nk:]).max() <= 1e-12 * np.abs(ak).max()
@@ -239,4 +326,41 @@ def test_sparse_table3_shape_f32(wp):
     assert rel_fro(host(res.shat), sh_ref) <= 1e-5
     assert rel_fro(ak, ak_ref) <= 1e-5
     assert abs(orc.psnr(x, ak) - orc.psnr(x, ak_ref)) <= 0.01
-    assert host(res.orth_err).max() <= 1e-4
+    assert host(res.orth_err).max() <= svd_bars(orc.lift_fwd(x, 5)[:6], 32, "f32")["orth"]
+
+
+@pytest.mark.parametrize("k", [96, 192])
+def test_sparse_table3_shape_high_rank(wp, k):
+    # Table 3 cube at rank 96 and at full rank 192: the 192-row recovered
+    # factor goes through the k > 64 polish.
+    import torch
+    from paper_2601_08228_amd import synth
+    x = cast(synth.hsi_like(256, 192, 96, seed=31), np.float32)
+    res = wp.w_svd_sparse(to_dev(x, torch.float32), 5, k)
+    torch.cuda.synchronize()
+    assert host(res.info).min() > 0
+    _, sh_ref, _, ak_ref = orc.w_svd_sparse(x, 5, k)
+    bars = svd_bars(orc.lift_fwd(x, 5)[:6], k, "f32", L=5, p=96)
+    assert rel_fro(host(res.shat), sh_ref) <= bars["shat"]
+    assert rel_fro(host(res.ak), ak_ref) <= bars["ak"]
+    assert host(res.orth_err).max() <= bars["orth"]
+
+
+@pytest.mark.parametrize("shape,dtype", [((64, 96, 80), "f32"), ((8, 300, 70), "f64")])
+def test_timed_entry_matches_and_times_the_jacobi(wp, shape, dtype):
+    # w_svd_timed gives w_svd's results bit for bit (register and block
+    # kernels) and records its two events around the Jacobi stage, inside the
+    # whole call.
+    import torch
+    td = torch.float32 if dtype == "f32" else torch.float64
+    a = to_dev(np.random.default_rng(12).standard_normal(shape), td)
+    ref = wp.w_svd(a, 2, 6)
+    e0, e1, c0, c1 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
+    c0.record()
+    got = wp.w_svd_timed(a, 2, 6, e0, e1)
+    c1.record()
+    torch.cuda.synchronize()
+    for f, r in zip(got[:5], ref[:5]):
+        assert torch.equal(f, r)
+    jac, whole = e0.elapsed_time(e1), c0.elapsed_time(c1)
+    assert 0 < jac <= whole

@@ -145,3 +145,17 @@ def test_transpose_invariance():
 def test_rejects_bad_levels(p, L):
     with pytest.raises(ValueError):
         orc.check_levels(p, L)
+
+
+def test_parseval_weights_of_the_test_helper():
+    # The weights the GPU tests use to combine per-slice bars satisfy the
+    # weighted Parseval identity with the oracle's transform, for every level.
+    from gpu_helpers import parseval_weights
+    rng = np.random.default_rng(17)
+    for p, L in [(16, 0), (16, 1), (16, 4), (96, 5), (24, 3)]:
+        x = rng.standard_normal((p, 3, 5))
+        xh = orc.lift_fwd(x, L)
+        w = parseval_weights(p, L)
+        lhs = float(np.sum(x * x))
+        rhs = float(np.sum(w * np.sum(xh * xh, axis=(1, 2))))
+        assert abs(lhs - rhs) <= 1e-12 * lhs
