@@ -54,6 +54,7 @@ typedef int wp_status;
 #define WP_EWORKSPACE  -5   /* workspace smaller than the *_workspace() query    */
 #define WP_ELAUNCH     -6   /* a HIP launch or runtime call failed               */
 #define WP_ENOCONV     -7   /* reported by callers when a Jacobi slice did not converge */
+#define WP_ESCRATCH    -8   /* w_product_noalloc: the call needs more than its fixed scratch */
 
 #define WP_F64 0
 #define WP_F32 1
@@ -198,6 +199,27 @@ wp_status w_product(const void* a, const void* b, void* c,
 /* Workspace bytes for w_product (0 on invalid arguments). */
 size_t w_product_workspace(int64_t n1, int64_t n2, int64_t n3, int64_t p, int L,
                            int dtype, int gemm);
+
+/* w_product for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same kernels and results as w_product, with the workspace taken from a fixed
+ * device array inside the library instead of a caller buffer.  The caller
+ * still passes (and owns) a, b and c.  The array holds
+ * w_product_noalloc_scratch_bytes() = 128 MiB; a call whose
+ * w_product_workspace(...) is larger returns WP_ESCRATCH before any HIP call.
+ * Each device the library runs on holds its own array until the process ends
+ * (its address is looked up on the first call on that device, with that device
+ * current).  No call allocates or frees memory.  Every call on one device
+ * shares that device's array and leaves its contents behind (nothing in it
+ * needs to start at zero): calls that overlap on one device (on different
+ * streams, or from different host threads) race and must be ordered by the
+ * caller. */
+wp_status w_product_noalloc(const void* a, const void* b, void* c,
+                            int64_t n1, int64_t n2, int64_t n3, int64_t p, int L,
+                            int trans_a, int trans_b, int dtype, int gemm, void* stream);
+
+/* Bytes of the fixed device scratch of w_product_noalloc. */
+size_t w_product_noalloc_scratch_bytes(void);
 
 /* ---- w-svd (Alg. 2, Thm 2.5) ------------------------------------------------
  * Truncated SVD of every coefficient slice of W(A), A (p, n1, n2), by one-sided

@@ -9,7 +9,8 @@ call and a missing build raises ImportError.
 from .wprod import (  # noqa: F401
     w_transform, w_itransform, w_transform_adj, w_itransform_adj, w_transform_split,
     w_itransform_adj_split, w_face_product, w_face_product_split, w_face_product_gemm,
-    w_face_product_workspace, w_product, w_product_workspace, w_svd, w_svd_timed,
+    w_face_product_workspace, w_product, w_product_workspace, w_product_noalloc,
+    w_product_noalloc_scratch_bytes, w_svd, w_svd_timed,
     w_svd_workspace, w_svd_sparse, w_svd_sparse_workspace,
     SvdResult, w_pinv, w_pinv_workspace, w_transform_scheme, w_transform_scheme_split,
     w_product_scheme, w_product_scheme_workspace,

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libwprod.so")
 # Status codes and enums of include/wprod.h.
 WP_OK = 0
 WP_ENOCONV = -7
+WP_ESCRATCH = -8
 WP_F64 = 0
 WP_F32 = 1
 GEMM_MODES = {"native": 0, "bf16": 1, "bf16x3": 2}
@@ -45,6 +46,9 @@ SIGNATURES = {
     "w_product": (_c_int, [_vp, _vp, _vp, _c_i64, _c_i64, _c_i64, _c_i64, _c_int, _c_int, _c_int,
                            _c_int, _c_int, _vp, _sz, _vp]),
     "w_product_workspace": (_sz, [_c_i64, _c_i64, _c_i64, _c_i64, _c_int, _c_int, _c_int]),
+    "w_product_noalloc": (_c_int, [_vp, _vp, _vp, _c_i64, _c_i64, _c_i64, _c_i64, _c_int, _c_int,
+                                   _c_int, _c_int, _c_int, _vp]),
+    "w_product_noalloc_scratch_bytes": (_sz, []),
     "w_svd": (_c_int, [_vp, _c_i64, _c_i64, _c_i64, _c_int, _c_int, _vp, _vp, _vp, _vp, _c_int,
                        _vp, _vp, _c_int, _vp, _sz, _vp]),
     "w_svd_workspace": (_sz, [_c_i64, _c_i64, _c_i64, _c_int, _c_int, _c_int]),

@@ -2,8 +2,18 @@
 // call), workspace carving and kernel dispatch.  See include/wprod.h for the
 // contract of each call.
 
+#include <mutex>
+
 #include "wprod.h"
 #include "wp_internal.h"
+
+// Device scratch of w_product_noalloc: one fixed array, 256-byte aligned, on
+// every device the library runs on, held until the process ends.  Host code
+// never passes the name `scratch` to a kernel or a copy (on the host it only
+// names the symbol); it uses the device address that hipGetSymbolAddress
+// returns for the current device (scratch_on_current_device below).
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -184,6 +194,70 @@ inline wp_status check_modes(int dtype, int gemm) {
   return WP_OK;
 }
 
+// Device address of `scratch` on the calling thread's current device, looked
+// up once per device (with that device current) and kept.
+constexpr int kMaxDevices = 64;
+struct ScratchSlot {
+  std::once_flag once;
+  void* ptr = nullptr;
+  hipError_t err = hipSuccess;
+};
+ScratchSlot g_scratch[kMaxDevices];
+
+wp_status scratch_on_current_device(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return WP_ELAUNCH;
+  ScratchSlot& sl = g_scratch[dev];
+  std::call_once(sl.once, [&sl] {
+    sl.err = hipGetSymbolAddress(&sl.ptr, HIP_SYMBOL(scratch));
+  });
+  if (sl.err != hipSuccess || sl.ptr == nullptr) return WP_ELAUNCH;
+  *out = sl.ptr;
+  return WP_OK;
+}
+
+// Enqueues the w-product on `stream` with the workspace `ws` laid out by pl
+// (arguments already validated).
+wp_status enqueue_product(const void* a, const void* b, void* c, int64_t n1, int64_t n2,
+                          int64_t n3, int64_t p, int L, int trans_a, int trans_b, int dtype,
+                          int gemm, const ProductPlan& pl, void* ws, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = reinterpret_cast<char*>(wp::align_up(reinterpret_cast<uintptr_t>(ws), kAlign));
+  // Stored shapes: A is (p, n1, n2) or (p, n2, n1); the transform only sees
+  // n1*n2 positions per slice either way (Thm 2.1).
+  const int64_t Pa = n1 * n2, Pb = n2 * n3, Pc = n1 * n3;
+  hipError_t e = hipSuccess;
+  if (gemm == WP_GEMM_NATIVE) {
+    void* ah = base + pl.ah;
+    void* bh = base + pl.bh;
+    void* ch = base + pl.ch;
+    if (dtype == WP_F64) {
+      e = wp::launch_lift_f64(LiftKind::kForward, static_cast<const double*>(a), static_cast<double*>(ah), Pa, p, L, s);
+      if (e == hipSuccess) e = wp::launch_lift_f64(LiftKind::kForward, static_cast<const double*>(b), static_cast<double*>(bh), Pb, p, L, s);
+      if (e == hipSuccess) e = wp::launch_face_f64(static_cast<const double*>(ah), static_cast<const double*>(bh), static_cast<double*>(ch), n1, n2, n3, p, trans_a != 0, trans_b != 0, s);
+      if (e == hipSuccess) e = wp::launch_lift_f64(LiftKind::kInverse, static_cast<const double*>(ch), static_cast<double*>(c), Pc, p, L, s);
+    } else {
+      e = wp::launch_lift_f32(LiftKind::kForward, static_cast<const float*>(a), static_cast<float*>(ah), Pa, p, L, s);
+      if (e == hipSuccess) e = wp::launch_lift_f32(LiftKind::kForward, static_cast<const float*>(b), static_cast<float*>(bh), Pb, p, L, s);
+      if (e == hipSuccess) e = wp::launch_face_f32(static_cast<const float*>(ah), static_cast<const float*>(bh), static_cast<float*>(ch), n1, n2, n3, p, trans_a != 0, trans_b != 0, s);
+      if (e == hipSuccess) e = wp::launch_lift_f32(LiftKind::kInverse, static_cast<const float*>(ch), static_cast<float*>(c), Pc, p, L, s);
+    }
+  } else {
+    const bool x3 = gemm == WP_GEMM_BF16X3;
+    uint16_t* ahi = reinterpret_cast<uint16_t*>(base + pl.ah);
+    uint16_t* alo = x3 ? reinterpret_cast<uint16_t*>(base + pl.ah_lo) : nullptr;
+    uint16_t* bhi = reinterpret_cast<uint16_t*>(base + pl.bh);
+    uint16_t* blo = x3 ? reinterpret_cast<uint16_t*>(base + pl.bh_lo) : nullptr;
+    float* ch = reinterpret_cast<float*>(base + pl.ch);
+    e = wp::launch_lift_f32_split(LiftKind::kForward, static_cast<const float*>(a), ahi, alo, Pa, p, L, s);
+    if (e == hipSuccess) e = wp::launch_lift_f32_split(LiftKind::kForward, static_cast<const float*>(b), bhi, blo, Pb, p, L, s);
+    if (e == hipSuccess) e = wp::launch_face_bf16(ahi, alo, bhi, blo, ch, n1, n2, n3, p, trans_a != 0, trans_b != 0, x3, s);
+    if (e == hipSuccess) e = wp::launch_lift_f32(LiftKind::kInverse, ch, static_cast<float*>(c), Pc, p, L, s);
+  }
+  return from_hip(e);
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -198,6 +272,8 @@ const char* w_status_string(wp_status s) {
     case WP_EWORKSPACE: return "WP_EWORKSPACE: workspace too small";
     case WP_ELAUNCH: return "WP_ELAUNCH: HIP launch or runtime call failed";
     case WP_ENOCONV: return "WP_ENOCONV: a Jacobi slice did not converge";
+    case WP_ESCRATCH:
+      return "WP_ESCRATCH: the call needs more device scratch than w_product_noalloc holds";
   }
   return "unknown wp_status";
 }
@@ -345,40 +421,30 @@ wp_status w_product(const void* a, const void* b, void* c, int64_t n1, int64_t n
   if (overlap(rc, ra) || overlap(rc, rb) || overlap(rw, ra) || overlap(rw, rb) || overlap(rw, rc))
     return WP_EALIAS;
 
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  char* base = reinterpret_cast<char*>(wp::align_up(reinterpret_cast<uintptr_t>(ws), kAlign));
-  // Stored shapes: A is (p, n1, n2) or (p, n2, n1); the transform only sees
-  // n1*n2 positions per slice either way (Thm 2.1).
-  const int64_t Pa = n1 * n2, Pb = n2 * n3, Pc = n1 * n3;
-  hipError_t e = hipSuccess;
-  if (gemm == WP_GEMM_NATIVE) {
-    void* ah = base + pl.ah;
-    void* bh = base + pl.bh;
-    void* ch = base + pl.ch;
-    if (dtype == WP_F64) {
-      e = wp::launch_lift_f64(LiftKind::kForward, static_cast<const double*>(a), static_cast<double*>(ah), Pa, p, L, s);
-      if (e == hipSuccess) e = wp::launch_lift_f64(LiftKind::kForward, static_cast<const double*>(b), static_cast<double*>(bh), Pb, p, L, s);
-      if (e == hipSuccess) e = wp::launch_face_f64(static_cast<const double*>(ah), static_cast<const double*>(bh), static_cast<double*>(ch), n1, n2, n3, p, trans_a != 0, trans_b != 0, s);
-      if (e == hipSuccess) e = wp::launch_lift_f64(LiftKind::kInverse, static_cast<const double*>(ch), static_cast<double*>(c), Pc, p, L, s);
-    } else {
-      e = wp::launch_lift_f32(LiftKind::kForward, static_cast<const float*>(a), static_cast<float*>(ah), Pa, p, L, s);
-      if (e == hipSuccess) e = wp::launch_lift_f32(LiftKind::kForward, static_cast<const float*>(b), static_cast<float*>(bh), Pb, p, L, s);
-      if (e == hipSuccess) e = wp::launch_face_f32(static_cast<const float*>(ah), static_cast<const float*>(bh), static_cast<float*>(ch), n1, n2, n3, p, trans_a != 0, trans_b != 0, s);
-      if (e == hipSuccess) e = wp::launch_lift_f32(LiftKind::kInverse, static_cast<const float*>(ch), static_cast<float*>(c), Pc, p, L, s);
-    }
-  } else {
-    const bool x3 = gemm == WP_GEMM_BF16X3;
-    uint16_t* ahi = reinterpret_cast<uint16_t*>(base + pl.ah);
-    uint16_t* alo = x3 ? reinterpret_cast<uint16_t*>(base + pl.ah_lo) : nullptr;
-    uint16_t* bhi = reinterpret_cast<uint16_t*>(base + pl.bh);
-    uint16_t* blo = x3 ? reinterpret_cast<uint16_t*>(base + pl.bh_lo) : nullptr;
-    float* ch = reinterpret_cast<float*>(base + pl.ch);
-    e = wp::launch_lift_f32_split(LiftKind::kForward, static_cast<const float*>(a), ahi, alo, Pa, p, L, s);
-    if (e == hipSuccess) e = wp::launch_lift_f32_split(LiftKind::kForward, static_cast<const float*>(b), bhi, blo, Pb, p, L, s);
-    if (e == hipSuccess) e = wp::launch_face_bf16(ahi, alo, bhi, blo, ch, n1, n2, n3, p, trans_a != 0, trans_b != 0, x3, s);
-    if (e == hipSuccess) e = wp::launch_lift_f32(LiftKind::kInverse, ch, static_cast<float*>(c), Pc, p, L, s);
-  }
-  return from_hip(e);
+  return enqueue_product(a, b, c, n1, n2, n3, p, L, trans_a, trans_b, dtype, gemm, pl, ws, stream);
+}
+
+size_t w_product_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+wp_status w_product_noalloc(const void* a, const void* b, void* c, int64_t n1, int64_t n2,
+                            int64_t n3, int64_t p, int L, int trans_a, int trans_b, int dtype,
+                            int gemm, void* stream) {
+  wp_status st = check_modes(dtype, gemm);
+  if (st != WP_OK) return st;
+  FaceShapes fs{};
+  st = check_face(n1, n2, n3, p, trans_a, trans_b, &fs);
+  if (st != WP_OK) return st;
+  if (L < 0 || L > wp::kMaxLevels || p % (int64_t(1) << L) != 0) return WP_EINVAL;
+  const ProductPlan pl = plan_product(fs, dtype, gemm);
+  if (pl.total > kScratchBytes) return WP_ESCRATCH;
+  if (a == nullptr || b == nullptr || c == nullptr) return WP_ENULL;
+  const size_t es = dtype_size(dtype);
+  const Range ra = range_of(a, fs.a, es), rb = range_of(b, fs.b, es), rc = range_of(c, fs.c, es);
+  if (overlap(rc, ra) || overlap(rc, rb)) return WP_EALIAS;
+  void* ws = nullptr;
+  st = scratch_on_current_device(&ws);
+  if (st != WP_OK) return st;
+  return enqueue_product(a, b, c, n1, n2, n3, p, L, trans_a, trans_b, dtype, gemm, pl, ws, stream);
 }
 
 wp_status w_transform_scheme(const void* in, void* out, int64_t n1, int64_t n2, int64_t p, int L,

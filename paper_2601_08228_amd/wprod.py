@@ -20,7 +20,8 @@ __all__ = [
     "w_transform", "w_itransform", "w_transform_adj", "w_itransform_adj",
     "w_transform_split", "w_itransform_adj_split", "w_face_product",
     "w_face_product_split", "w_face_product_gemm", "w_face_product_workspace", "w_product",
-    "w_product_workspace", "w_svd", "w_svd_timed", "w_svd_workspace", "w_svd_sparse",
+    "w_product_workspace", "w_product_noalloc", "w_product_noalloc_scratch_bytes", "w_svd",
+    "w_svd_timed", "w_svd_workspace", "w_svd_sparse",
     "w_svd_sparse_workspace", "SvdResult", "w_pinv",
     "w_pinv_workspace", "SCHEME_KINDS", "w_transform_scheme", "w_transform_scheme_split",
     "w_product_scheme", "w_product_scheme_workspace",
@@ -249,6 +250,31 @@ def w_product(a, b, L, trans_a=False, trans_b=False, gemm="native", out=None, wo
                                    int(trans_b), _DT[a.dtype], mode, _ptr(workspace), nbytes,
                                    _stream(a))
     _lib.check("w_product", st)
+    return out
+
+
+def w_product_noalloc_scratch_bytes():
+    return int(_lib.load().w_product_noalloc_scratch_bytes())
+
+
+def w_product_noalloc(a, b, L, trans_a=False, trans_b=False, gemm="native", out=None):
+    """w_product with the library's fixed device scratch instead of a workspace:
+    the library allocates nothing (pass `out` to allocate nothing at all).
+    Calls that overlap on one device race on that scratch."""
+    _dev_tensor(a, "a", tuple(_DT))
+    _dev_tensor(b, "b", (a.dtype,))
+    if b.device != a.device:
+        raise ValueError("b is on %s; expected %s" % (b.device, a.device))
+    p, n1, n2, n3 = _face_dims(a, b, trans_a, trans_b)
+    if out is None:
+        out = torch.empty((p, n1, n3), dtype=a.dtype, device=a.device)
+    else:
+        _out_tensor(out, "out", (p, n1, n3), a.dtype, a.device)
+    with torch.cuda.device(a.device):
+        st = _lib.load().w_product_noalloc(_ptr(a), _ptr(b), _ptr(out), n1, n2, n3, p, int(L),
+                                           int(trans_a), int(trans_b), _DT[a.dtype],
+                                           _lib.GEMM_MODES[gemm], _stream(a))
+    _lib.check("w_product_noalloc", st)
     return out
 
 
