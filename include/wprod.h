@@ -10,9 +10,11 @@
  * Conventions shared by every entry point
  * ----------------------------------------
  * Memory.  Every tensor pointer is a DEVICE pointer on the calling thread's
- *   current HIP device, allocated and owned by the caller.  The library keeps
- *   no global state and allocates no device memory; where scratch is needed
- *   the caller passes a workspace whose size a *_workspace() query returns.
+ *   current HIP device, allocated and owned by the caller.  The library
+ *   allocates no device memory; where scratch is needed the caller passes a
+ *   workspace whose size a *_workspace() query returns.  Its only state is
+ *   the fixed device scratch of w_product_noalloc (and, per device, that
+ *   array's address and a kernel attribute, set on first use).
  * Layout.  A tensor X in R^{n1 x n2 x p} is p contiguous row-major n1 x n2
  *   frontal slices: X[i, j, k] (0-based) lives at element k*n1*n2 + i*n2 + j
  *   (a C-contiguous array of shape (p, n1, n2)).  A coefficient tensor has
