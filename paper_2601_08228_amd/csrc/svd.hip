@@ -120,6 +120,26 @@ __device__ __forceinline__ int rotation(double al, double be, double ga, double 
   return 1;
 }
 
+// rotation() that also returns the tangent t (0 below the threshold), for
+// updating the two column norms: with gamma zeroed, |w_i'|^2 = alpha - t gamma
+// and |w_j'|^2 = beta + t gamma.
+__device__ __forceinline__ int rotation_t(double al, double be, double ga, double tol, double& c,
+                                          double& s, double& t) {
+  c = 1.0;
+  s = 0.0;
+  t = 0.0;
+  if (!(isfinite(al) && isfinite(be) && isfinite(ga))) return 2;
+  if (!(ga * ga > tol * tol * (al * be))) return 0;
+  const double d = be - al;
+  const double g2 = 2.0 * ga;
+  const double q = fma(d, d, g2 * g2);
+  const double h = q * rsqrt64(q);
+  t = copysign(1.0, d) * g2 * rcp64(fabs(d) + h);
+  c = rsqrt64(fma(t, t, 1.0));
+  s = c * t;
+  return 1;
+}
+
 // Singular values, ranking and the k leading columns of the factor formed by
 // W (column c at W + c * mr), called by every thread of the workgroup: U (and
 // U * sigma) when n1 >= n2, vhat otherwise.  The other factor is recovered
@@ -533,6 +553,8 @@ __global__ __launch_bounds__(kJacobiThreads) void bj_emit_kernel(
 }
 
 constexpr int kUnits = 4 * kJacobiWaves;  // 16-lane rows per workgroup
+// Blocks of J rounds between two foldings of the column scales (register kernel).
+constexpr int kRescaleBlocks = 16;
 
 // Register-resident Jacobi on W only.  A unit is one 16-lane DPP row; column
 // entries are spread over its lanes, RPL rows per lane (row = lane16 + 16 t,
@@ -541,11 +563,17 @@ constexpr int kUnits = 4 * kJacobiWaves;  // 16-lane rows per workgroup
 // round.  nunits * J slots in total; positions beyond nc hold zero columns,
 // which never rotate.
 //
-// Per round and pair: alpha, beta and gamma as 16-lane row sums (FP32 data:
-// FP32 lane partials and FP32 row sums, at most RPL + 4 rounding steps, well
-// under the threshold sqrt(mr) * 2^-24 in the typical case; FP64 data: FP64
-// throughout).  The J angles of a unit are then evaluated together in FP64,
-// pair j in lane j, and broadcast to the row.
+// Per round and pair: gamma as a 16-lane row sum (FP32 data: FP32 lane
+// partials and FP32 row sums, at most RPL + 4 rounding steps; FP64 data: FP64
+// throughout); the two column norms alpha, beta are not summed again but
+// carried with the columns: each slot keeps its column's squared norm (the
+// same value in the unit's 16 lanes), summed exactly at the start of every
+// sweep and updated after each rotation by alpha - t gamma, beta + t gamma
+// (exact for the rotation that zeroes gamma).  That saves two of the three
+// dot products of a pair; the drift of the carried norms within one sweep
+// costs at most one sweep more on the hyperspectral-like test tensor.  The
+// J angles of a unit are evaluated together in FP64, pair j in lane j, and
+// the cosines, sines and updated norms are broadcast to the row.
 //
 // Circle method: position 0 (unit 0, top slot 0) is fixed and the other
 // positions advance one step per round (top q -> top q+1, top H-1 -> bottom
@@ -584,6 +612,16 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
   __shared__ int s_bad;
   __shared__ double s_sigma[1024];
   __shared__ int s_order[1024];
+  // Squared norm of every column, indexed by column (the columns move
+  // between units, their norms stay in place); shares the storage of the
+  // singular values, which are formed only after the sweeps.
+  // With them, the scales d of the columns (w = d x) and their inverses e,
+  // indexed the same way.
+  constexpr int kPos = 2 * kUnits * 4;
+  static_assert(kPos * (sizeof(T) + 2 * sizeof(double)) <= sizeof(s_sigma), "fits");
+  double* const s_d = s_sigma;
+  double* const s_e = s_sigma + kPos;
+  T* const s_norm = reinterpret_cast<T*>(s_sigma + 2 * kPos);
 
   // Column held by slot q after r rounds (0 <= r < CIRC): position p starts
   // with column p and the circle advances one position per round.
@@ -686,54 +724,114 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
   // A sweep runs 2H = CIRC + 1 rounds, a whole number of J-round blocks, so
   // the register renaming is the identity at every sweep end (the extra
   // round repeats the pairs of the sweep's first round).
+  // Lane j of a unit (j < J) keeps the norms and scales of the unit's pair j:
+  // top position q0 + j and the bottom position below it.
+  const int jl = lane16 & M;
+  int rc = 0;  // rounds since the start, mod CIRC (the circle's position)
+  // Folds each scale into its column (w = d x), sets d = e = 1 and, at a
+  // sweep's start, sums the exact squared norms; at a multiple of J rounds the
+  // renaming is the identity, so slot j holds logical top / bottom j.
+  auto rescale = [&](bool norms) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int it = active ? top_id(q0 + j, rc) : 0;
+      const int ib = active ? bot_id(q0 + j, rc) : 0;
+      const T dt = T(s_d[it]), db = T(s_d[ib]);
+      T pa = 0, pb = 0;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        tc[j][t] *= dt;
+        bc[j][t] *= db;
+        pa = fma(tc[j][t], tc[j][t], pa);
+        pb = fma(bc[j][t], bc[j][t], pb);
+      }
+      if (norms) {
+        pa = row_sum16(pa);
+        pb = row_sum16(pb);
+      }
+      if (active && lane16 == 0) {
+        s_d[it] = 1.0;
+        s_e[it] = 1.0;
+        s_d[ib] = 1.0;
+        s_e[ib] = 1.0;
+        if (norms) {
+          s_norm[it] = pa;
+          s_norm[ib] = pb;
+        }
+      }
+    }
+  };
+  for (int q = threadIdx.x; q < 2 * H; q += kJacobiThreads) {
+    s_d[q] = 1.0;
+    s_e[q] = 1.0;
+  }
+  __syncthreads();
   for (;;) {
     for (int blk = 0; blk < 2 * nunits; ++blk) {
+      // Exact norms at the start of every sweep; the scales are folded in
+      // every kRescaleBlocks blocks, which bounds the growth of the stored
+      // columns (at most sqrt(2) per rotation) to 2^(J kRescaleBlocks / 2).
+      if (blk % kRescaleBlocks == 0) rescale(blk == 0);
       static_for<0, J>([&](auto RR) {
         constexpr int rr = decltype(RR)::value;
         {
-          T al[J], be[J], ga[J];
+          // gamma of the scaled columns x, y of each pair.
+          T ga[J];
 #pragma unroll
           for (int j = 0; j < J; ++j) {
             const T* x = tc[(j - rr) & M];
             const T* y = bc[(j + rr) & M];
-            T pa = 0, pb = 0, pg = 0;
+            T pg = 0;
 #pragma unroll
-            for (int t = 0; t < RPL; ++t) {
-              pa = fma(x[t], x[t], pa);
-              pb = fma(y[t], y[t], pb);
-              pg = fma(x[t], y[t], pg);
-            }
-            al[j] = row_sum16(pa);
-            be[j] = row_sum16(pb);
+            for (int t = 0; t < RPL; ++t) pg = fma(x[t], y[t], pg);
             ga[j] = row_sum16(pg);
           }
-          // Pair j's angle in lane j.
-          T sa = al[0], sb = be[0], sg = ga[0];
+          // Pair j in lane j: w_i = d_i x_i, w_j = d_j x_j, so the inner
+          // product of the columns is d_i d_j (x_i . x_j); alpha and beta
+          // are the carried squared norms of w_i, w_j.
+          const int id_t = active ? top_id(q0 + jl, rc) : 0;
+          const int id_b = active ? bot_id(q0 + jl, rc) : 0;
+          const double al = double(s_norm[id_t]), be = double(s_norm[id_b]);
+          const double di = s_d[id_t], dj = s_d[id_b];
+          const double ei = s_e[id_t], ej = s_e[id_b];
+          T sg = ga[0];
 #pragma unroll
-          for (int j = 1; j < J; ++j) {
-            if (lane16 == j) {
-              sa = al[j];
-              sb = be[j];
-              sg = ga[j];
-            }
-          }
-          double cd, sd;
-          const int flag = rotation(double(sa), double(sb), double(sg), tol, cd, sd);
+          for (int j = 1; j < J; ++j)
+            if (lane16 == j) sg = ga[j];
+          const double gam = double(sg) * di * dj;
+          double cd, sd, td;
+          const int flag = rotation_t(al, be, gam, tol, cd, sd, td);
           if (lane16 < J) {
             my_rot += flag == 1;
             my_bad |= flag == 2;
           }
-          const T cl = T(cd), sl = T(sd);
+          // Scaled rotation as two shears, each an FMA in place:
+          //   x_j' = x_j + b x_i,  b = t d_i / d_j,             d_j' = c d_j;
+          //   x_i' = x_i - a x_j', a = t d_j / (d_i (1 + t^2)), d_i' = d_i / c;
+          // then d_i' x_i' = c w_i - s w_j and d_j' x_j' = s w_i + c w_j (the
+          // rotation that zeroes gamma).  The stored values of one column grow
+          // by 1 / c <= sqrt(2) and those of the other shrink by c.  e = 1 / d is
+          // carried too (1 / c = c (1 + t^2)).
+          const double ic = cd * fma(td, td, 1.0);
+          const T fb = T(td * di * ej);
+          const T fa = T(td * dj * ei * cd * cd);
+          if (active && lane16 < J && flag == 1) {
+            s_norm[id_t] = T(fma(-td, gam, al));
+            s_norm[id_b] = T(fma(td, gam, be));
+            s_d[id_t] = ic * di;
+            s_d[id_b] = cd * dj;
+            s_e[id_t] = cd * ei;
+            s_e[id_b] = ic * ej;
+          }
           static_for<0, J>([&](auto JJ) {
             constexpr int j = decltype(JJ)::value;
-            const T c = row_bcast<j>(cl), s = row_bcast<j>(sl);
+            const T ax = row_bcast<j>(fa), bx = row_bcast<j>(fb);
             T* x = tc[(j - rr) & M];
             T* y = bc[(j + rr) & M];
 #pragma unroll
             for (int t = 0; t < RPL; ++t) {
-              const T cu = c * x[t], su = s * x[t];
-              x[t] = fma(-s, y[t], cu);
-              y[t] = fma(c, y[t], su);
+              y[t] = fma(bx, x[t], y[t]);
+              x[t] = fma(-ax, y[t], x[t]);
             }
           });
           // Outgoing columns: logical top J-1 and bottom 0 (and unit 0's fixed top 0).
@@ -774,6 +872,7 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
           }
         }
         par ^= 1;
+        rc = rc + 1 == CIRC ? 0 : rc + 1;
       });
     }
     // End of a sweep: converged if no pair rotated.
@@ -791,6 +890,7 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
       break;
     }
   }
+  rescale(false);  // the columns of W themselves
 
   if (active) {
     // After sw sweeps the circle has advanced sw * 2H = sw (mod CIRC) positions.
@@ -972,12 +1072,13 @@ __device__ __forceinline__ double gram_dev(const double* __restrict__ G, int k, 
 constexpr int kPolishSteps = 4;
 
 // Deviation thresholds of the polish for n rows of T: at or below t_done the
-// factor is orthonormal to the rounding of T; from at or below t_last one
-// more step reaches it.
+// factor is orthonormal to the rounding of T (storing a column in T moves the
+// Gram entries by up to 2 u_T, and the FP64 Gram itself is accurate to about
+// sqrt(n) u_64); from at or below t_last one more step reaches it.
 template <typename T>
 __host__ __device__ inline void polish_thresholds(int n, double& t_done, double& t_last) {
   const double u = Unit<T>::value;
-  t_done = 4.0 * (sqrt(double(n)) + 2.0) * u;
+  t_done = 4.0 * u + 4.0 * sqrt(double(n)) * Unit<double>::value;
   t_last = 0.25 * sqrt(u);
 }
 
