@@ -918,88 +918,131 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
 // vhat_i = A^T u_i / sigma_i (n1 >= n2), or u_i = A vhat_i / sigma_i (n1 < n2),
 // accumulated in FP64 from the coefficients.  In the second case the sign
 // convention (largest |U| entry positive) is applied here to both columns,
-// and U * sigma is written for the rebuild.  One workgroup per (slice, i);
-// columns with sigma_i at or below max(n1, n2) u sigma_1 come out zero.
+// and U * sigma is written for the rebuild.  One workgroup per (slice, block
+// of kRecCols columns), which reads the slice once for the block; columns with
+// sigma_i at or below max(n1, n2) u sigma_1 come out zero.
+constexpr int kRecCols = 4;  // recovered columns per workgroup
 template <typename T>
 __global__ __launch_bounds__(256) void recover_kernel(const T* __restrict__ ah, SvdDims d,
                                                       T* __restrict__ uhat,
                                                       const T* __restrict__ shat,
                                                       T* __restrict__ vhat, T* __restrict__ us) {
   const int k = d.k;
-  const int slice = blockIdx.x / k;
-  const int i = blockIdx.x % k;
+  const int slice = blockIdx.x;
+  const int i0 = blockIdx.y * kRecCols;
   const int mr = d.mr, nc = d.nc;
   const T* A = ah + int64_t(slice) * d.n1 * d.n2;
   T* U = uhat + int64_t(slice) * d.n1 * k;
   T* Vo = vhat + int64_t(slice) * d.n2 * k;
-  const T* src = d.trans ? Vo : U;  // the column formed from W, mr entries
-  T* dst = d.trans ? U : Vo;        // the column recovered here, nc entries
+  const T* src = d.trans ? Vo : U;  // the columns formed from W, mr entries
+  T* dst = d.trans ? U : Vo;        // the columns recovered here, nc entries
   constexpr int kOut = kMaxSide / 256;
-  __shared__ double s_src[kMaxSide];
-  __shared__ double s_best[256];
-  __shared__ int s_row[256];
-  __shared__ double s_val[256];
+  __shared__ double s_src[kRecCols][kMaxSide];
+  __shared__ double s_best[kRecCols][256];
+  __shared__ int s_row[kRecCols][256];
+  __shared__ double s_val[kRecCols][256];
   // Columns of singular values at or below the numerical rank cut
   // max(n1, n2) u sigma_1 (the cut of the pseudo-inverse) are not recovered
   // (zero): A^T u_i / sigma_i would amplify the rounding of u_i beyond one.
-  const double sg = double(shat[int64_t(slice) * k + i]);
   const double cut = double(mr) * Unit<T>::value * double(shat[int64_t(slice) * k]);
-  const double inv = sg > cut ? 1.0 / sg : 0.0;
-  for (int t = threadIdx.x; t < mr; t += 256) s_src[t] = double(src[int64_t(t) * k + i]);
+  double sg[kRecCols], inv[kRecCols];
+#pragma unroll
+  for (int c = 0; c < kRecCols; ++c) {
+    const int i = i0 + c < k ? i0 + c : i0;
+    sg[c] = double(shat[int64_t(slice) * k + i]);
+    inv[c] = (i0 + c < k && sg[c] > cut) ? 1.0 / sg[c] : 0.0;
+  }
+  for (int t = threadIdx.x; t < mr; t += 256)
+#pragma unroll
+    for (int c = 0; c < kRecCols; ++c)
+      s_src[c][t] = i0 + c < k ? double(src[int64_t(t) * k + i0 + c]) : 0.0;
   __syncthreads();
-  double out[kOut];
-  double best = -1.0, bval = 0.0;
-  int brow = 0x7fffffff;
+  double out[kOut][kRecCols];
+  double best[kRecCols], bval[kRecCols];
+  int brow[kRecCols];
+#pragma unroll
+  for (int c = 0; c < kRecCols; ++c) {
+    best[c] = -1.0;
+    bval[c] = 0.0;
+    brow[c] = 0x7fffffff;
+  }
 #pragma unroll
   for (int j = 0; j < kOut; ++j) {
     const int r = threadIdx.x + 256 * j;
-    double acc = 0;
+    double acc[kRecCols] = {};
     if (r < nc) {
+      // Each element of the slice is read once for all kRecCols columns.
       if (d.trans)
-        for (int t = 0; t < mr; ++t) acc = fma(double(A[int64_t(r) * d.n2 + t]), s_src[t], acc);
+        for (int t = 0; t < mr; ++t) {
+          const double a = double(A[int64_t(r) * d.n2 + t]);
+#pragma unroll
+          for (int c = 0; c < kRecCols; ++c) acc[c] = fma(a, s_src[c][t], acc[c]);
+        }
       else
-        for (int t = 0; t < mr; ++t) acc = fma(double(A[int64_t(t) * d.n2 + r]), s_src[t], acc);
-      acc *= inv;
-      if (fabs(acc) > best) {
-        best = fabs(acc);
-        brow = r;
-        bval = acc;
+        for (int t = 0; t < mr; ++t) {
+          const double a = double(A[int64_t(t) * d.n2 + r]);
+#pragma unroll
+          for (int c = 0; c < kRecCols; ++c) acc[c] = fma(a, s_src[c][t], acc[c]);
+        }
+#pragma unroll
+      for (int c = 0; c < kRecCols; ++c) {
+        acc[c] *= inv[c];
+        if (fabs(acc[c]) > best[c]) {
+          best[c] = fabs(acc[c]);
+          brow[c] = r;
+          bval[c] = acc[c];
+        }
       }
     }
-    out[j] = acc;
+#pragma unroll
+    for (int c = 0; c < kRecCols; ++c) out[j][c] = acc[c];
   }
-  double sgn = 1.0;
+  double sgn[kRecCols];
+#pragma unroll
+  for (int c = 0; c < kRecCols; ++c) sgn[c] = 1.0;
   if (d.trans) {
-    // Largest |U| entry over the column, lowest row on ties.
-    s_best[threadIdx.x] = best;
-    s_row[threadIdx.x] = brow;
-    s_val[threadIdx.x] = bval;
+    // Largest |U| entry over each column, lowest row on ties.
+#pragma unroll
+    for (int c = 0; c < kRecCols; ++c) {
+      s_best[c][threadIdx.x] = best[c];
+      s_row[c][threadIdx.x] = brow[c];
+      s_val[c][threadIdx.x] = bval[c];
+    }
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
       if (threadIdx.x < w) {
         const int o = threadIdx.x + w;
-        if (s_best[o] > s_best[threadIdx.x] ||
-            (s_best[o] == s_best[threadIdx.x] && s_row[o] < s_row[threadIdx.x])) {
-          s_best[threadIdx.x] = s_best[o];
-          s_row[threadIdx.x] = s_row[o];
-          s_val[threadIdx.x] = s_val[o];
-        }
+#pragma unroll
+        for (int c = 0; c < kRecCols; ++c)
+          if (s_best[c][o] > s_best[c][threadIdx.x] ||
+              (s_best[c][o] == s_best[c][threadIdx.x] && s_row[c][o] < s_row[c][threadIdx.x])) {
+            s_best[c][threadIdx.x] = s_best[c][o];
+            s_row[c][threadIdx.x] = s_row[c][o];
+            s_val[c][threadIdx.x] = s_val[c][o];
+          }
       }
       __syncthreads();
     }
-    sgn = s_val[0] < 0 ? -1.0 : 1.0;
+#pragma unroll
+    for (int c = 0; c < kRecCols; ++c) sgn[c] = s_val[c][0] < 0 ? -1.0 : 1.0;
   }
 #pragma unroll
   for (int j = 0; j < kOut; ++j) {
     const int r = threadIdx.x + 256 * j;
-    if (r < nc) {
-      const T x = T(sgn * out[j]);
-      dst[int64_t(r) * k + i] = x;
-      if (d.trans) us[int64_t(slice) * d.n1 * k + int64_t(r) * k + i] = T(x * T(sg));
-    }
+    if (r < nc)
+#pragma unroll
+      for (int c = 0; c < kRecCols; ++c) {
+        if (i0 + c >= k) continue;
+        const T x = T(sgn[c] * out[j][c]);
+        dst[int64_t(r) * k + i0 + c] = x;
+        if (d.trans) us[int64_t(slice) * d.n1 * k + int64_t(r) * k + i0 + c] = T(x * T(sg[c]));
+      }
   }
-  if (d.trans && sgn < 0)
-    for (int t = threadIdx.x; t < mr; t += 256) Vo[int64_t(t) * k + i] = T(-s_src[t]);
+  if (d.trans)
+#pragma unroll
+    for (int c = 0; c < kRecCols; ++c)
+      if (i0 + c < k && sgn[c] < 0)
+        for (int t = threadIdx.x; t < mr; t += 256) Vo[int64_t(t) * k + i0 + c] = T(-s_src[c][t]);
 }
 
 // Gram matrix G = X^T X (FP64) of one slice X (n x k row-major, k <= 64) for
@@ -1010,23 +1053,55 @@ constexpr int kGramRows = 64;
 template <typename T>
 __device__ __forceinline__ void gram_k64(const T* __restrict__ X, int n, int k, double (&acc)[16],
                                          double* s_blk) {
+  // Entry slots q < nq hold entries (the same for every thread: a uniform
+  // branch), and each slot's (a, b) is fixed over the rows.
+  const int nq = (k * k + 255) / 256;
+  int ia[16], ib[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0;
+  for (int q = 0; q < 16; ++q) {
+    acc[q] = 0;
+    const int e = threadIdx.x + 256 * q;
+    const bool in = e < k * k;
+    ia[q] = in ? e / k : 0;
+    ib[q] = in ? e - (e / k) * k : 0;
+  }
   for (int r0 = 0; r0 < n; r0 += kGramRows) {
     const int rows = n - r0 < kGramRows ? n - r0 : kGramRows;
     __syncthreads();
     for (int e = threadIdx.x; e < rows * k; e += 256) s_blk[e] = double(X[int64_t(r0) * k + e]);
     __syncthreads();
-    for (int r = 0; r < rows; ++r) {
-      const double* xr = s_blk + r * k;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int e = threadIdx.x + 256 * q;
-        if (e < k * k) {
-          const int a = e / k, b = e - a * k;
-          acc[q] = fma(xr[a], xr[b], acc[q]);
-        }
+    for (int q = 0; q < 16; ++q) {
+      if (q < nq) {
+        const double* xa = s_blk + ia[q];
+        const double* xb = s_blk + ib[q];
+        double s = acc[q];
+        for (int r = 0; r < rows; ++r) s = fma(xa[r * k], xb[r * k], s);
+        acc[q] = s;
       }
+    }
+  }
+  // Entries past k * k stay exactly zero (they multiplied row 0's column 0
+  // only in slots that are not used).
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    if (threadIdx.x + 256 * q >= k * k) acc[q] = 0;
+}
+
+// The same Gram matrix of a slice already in LDS as FP64 (n x k row-major).
+__device__ __forceinline__ void gram_lds(const double* __restrict__ s_x, int n, int k,
+                                         double (&acc)[16]) {
+  const int nq = (k * k + 255) / 256;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    acc[q] = 0;
+    const int e = threadIdx.x + 256 * q;
+    if (q < nq && e < k * k) {
+      const int a = e / k, b = e - a * k;
+      double s = 0;
+      for (int r = 0; r < n; ++r) s = fma(s_x[r * k + a], s_x[r * k + b], s);
+      acc[q] = s;
     }
   }
 }
@@ -1082,20 +1157,28 @@ __host__ __device__ inline void polish_thresholds(int n, double& t_done, double&
   t_last = 0.25 * sqrt(u);
 }
 
-// k <= 64: one workgroup per slice, G and M in LDS, the rows of X streamed
-// through LDS in blocks (each row's update reads only that row, so the blocks
-// are updated in place).
+// k <= 64: one workgroup per slice, G and M in LDS.  When the slice fits
+// (n k <= kPolishLds values) it is read into LDS once and every pass runs
+// from there; otherwise the rows are streamed through LDS in blocks (each
+// row's update reads only that row, so the blocks are updated in place).
+constexpr int kPolishLds = 8192;
 template <typename T>
 __global__ __launch_bounds__(256) void polish_kernel(T* __restrict__ x, int n, int k) {
   __shared__ double s_m[64 * 64];
-  __shared__ double s_blk[kGramRows * 64];
+  __shared__ double s_x[kPolishLds];
   __shared__ double s_red[256];
   T* X = x + int64_t(blockIdx.x) * n * k;
   double t_done, t_last;
   polish_thresholds<T>(n, t_done, t_last);
+  const bool whole = n * k <= kPolishLds;
+  if (whole)
+    for (int e = threadIdx.x; e < n * k; e += 256) s_x[e] = double(X[e]);
   for (int step = 0; step < kPolishSteps; ++step) {
     double acc[16];
-    gram_k64<T>(X, n, k, acc, s_blk);
+    if (whole)
+      gram_lds(s_x, n, k, acc);
+    else
+      gram_k64<T>(X, n, k, acc, s_x);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int e = threadIdx.x + 256 * q;
@@ -1108,21 +1191,47 @@ __global__ __launch_bounds__(256) void polish_kernel(T* __restrict__ x, int n, i
       const int a = e / k, b = e - a * k;
       s_m[e] = (a == b ? 1.5 : 0.0) - 0.5 * s_m[e];
     }
-    // Row blocks: stage, then X[r][i] = sum_j X[r][j] M[j][i]; consecutive
-    // threads take consecutive i, so M reads are conflict-free and X reads
-    // broadcast.
-    for (int r0 = 0; r0 < n; r0 += kGramRows) {
-      const int rows = n - r0 < kGramRows ? n - r0 : kGramRows;
-      T* Xb = X + int64_t(r0) * k;
+    // X[r][i] = sum_j X[r][j] M[j][i]; consecutive threads take consecutive i,
+    // so M reads are conflict-free and X reads broadcast.
+    if (whole) {
+      constexpr int kPer = kPolishLds / 256;
+      double nx[kPer];
       __syncthreads();
-      for (int e = threadIdx.x; e < rows * k; e += 256) s_blk[e] = double(Xb[e]);
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        double a2 = 0;
+        if (e < n * k) {
+          const int r = e / k, i = e - r * k;
+          const double* xr = s_x + r * k;
+          for (int j = 0; j < k; ++j) a2 = fma(xr[j], s_m[j * k + i], a2);
+        }
+        nx[q] = a2;
+      }
       __syncthreads();
-      for (int e = threadIdx.x; e < rows * k; e += 256) {
-        const int r = e / k, i = e - r * k;
-        const double* xr = s_blk + r * k;
-        double acc2 = 0;
-        for (int j = 0; j < k; ++j) acc2 = fma(xr[j], s_m[j * k + i], acc2);
-        Xb[e] = T(acc2);
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        if (e < n * k) {
+          const T v = T(nx[q]);
+          X[e] = v;
+          s_x[e] = double(v);  // the stored value, as the next pass reads it
+        }
+      }
+    } else {
+      for (int r0 = 0; r0 < n; r0 += kGramRows) {
+        const int rows = n - r0 < kGramRows ? n - r0 : kGramRows;
+        T* Xb = X + int64_t(r0) * k;
+        __syncthreads();
+        for (int e = threadIdx.x; e < rows * k; e += 256) s_x[e] = double(Xb[e]);
+        __syncthreads();
+        for (int e = threadIdx.x; e < rows * k; e += 256) {
+          const int r = e / k, i = e - r * k;
+          const double* xr = s_x + r * k;
+          double a2 = 0;
+          for (int j = 0; j < k; ++j) a2 = fma(xr[j], s_m[j * k + i], a2);
+          Xb[e] = T(a2);
+        }
       }
     }
     if (!(dev > t_last)) return;  // NaN: stop as well
@@ -1468,8 +1577,9 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
   e = hipGetLastError();
   if (e == hipSuccess && ev_end != nullptr) e = hipEventRecord(ev_end, s);
   if (e != hipSuccess || !second_factor) return e;
-  hipLaunchKernelGGL((recover_kernel<T>), dim3(unsigned(nsl * k)), dim3(256), 0, s, ah, d, uhat,
-                     shat, vhat, us);
+  hipLaunchKernelGGL((recover_kernel<T>),
+                     dim3(unsigned(nsl), unsigned((k + kRecCols - 1) / kRecCols)), dim3(256), 0, s,
+                     ah, d, uhat, shat, vhat, us);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
 
