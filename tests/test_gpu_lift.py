@@ -68,7 +68,8 @@ def test_f32_vs_oracle(wp, shape, kind):
 
 
 @pytest.mark.parametrize("kind", ["w_transform_split", "w_itransform_adj_split"])
-@pytest.mark.parametrize("shape", [(16, 32, 24, 2), (64, 33, 31, 6), (7, 9, 11, 0), (32, 64, 64, 3)])
+@pytest.mark.parametrize("shape", [(16, 32, 24, 2), (64, 33, 31, 6), (7, 9, 11, 0), (32, 64, 64, 3),
+                                   (16, 12, 5, 2), (256, 64, 40, 8)])
 def test_split_epilogue(wp, kind, shape):
     # hi = RNE_bf16(c) and lo = RNE_bf16(c - hi) of the FP32 coefficients the plain pass writes.
     import torch
