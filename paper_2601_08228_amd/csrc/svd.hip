@@ -400,6 +400,7 @@ __global__ __launch_bounds__(kBjThreads) void bj_round_kernel(T* __restrict__ wb
   constexpr int GL = kBjThreads / B;  // lanes per group
   constexpr int CAP = GL * RPL;       // rows per column slot
   __shared__ T s_x[B * CAP];
+  __shared__ double s_n[B];  // squared norms of the columns in the LDS slots
   const int slice = blockIdx.y;
   if (ctl[slice].state != 0 || !ctl[slice].live) return;
   int bi, bj;
@@ -410,53 +411,76 @@ __global__ __launch_bounds__(kBjThreads) void bj_round_kernel(T* __restrict__ wb
   int nrot = 0;
   bool bad = false;
 
-  // Rotation for the pair (x, y) (this lane's rows) from the group's sums.
-  auto angle = [&](const T (&x)[RPL], const T (&y)[RPL], double& c, double& s) {
-    T al = 0, be = 0, ga = 0;
+  auto norm2 = [&](const T (&x)[RPL]) -> double {
+    T a = 0;
 #pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-      al = fma(x[t], x[t], al);
-      be = fma(y[t], y[t], be);
-      ga = fma(x[t], y[t], ga);
-    }
-    al = group_sum<GL>(al);
-    be = group_sum<GL>(be);
-    ga = group_sum<GL>(ga);
-    const int f = rotation(double(al), double(be), double(ga), tol, c, s);
+    for (int t = 0; t < RPL; ++t) a = fma(x[t], x[t], a);
+    return double(group_sum<GL>(a));
+  };
+  // Rotation for the pair (x, y) (this lane's rows): gamma from the group's
+  // sum, the squared norms al, be carried with the columns and updated to
+  // those of the rotated pair (al - t gamma, be + t gamma).
+  auto angle = [&](const T (&x)[RPL], const T (&y)[RPL], double& al, double& be, double& c,
+                   double& s) {
+    T ga = 0;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) ga = fma(x[t], y[t], ga);
+    const double g64 = double(group_sum<GL>(ga));
+    double tt;
+    const int f = rotation_t(al, be, g64, tol, c, s, tt);
+    al = fma(-tt, g64, al);
+    be = fma(tt, g64, be);
     nrot += f == 1;
     bad |= f == 2;
   };
 
   T top[RPL], bot[RPL];
+  double ntop, nbot;
   if (round == 0) {
     // Pairs inside each block, J first then I: columns in LDS slots, B / 2
-    // groups rotate one pair each per sub-round.
+    // groups rotate one pair each per sub-round, streaming the two columns
+    // from LDS (once for gamma, once more to rotate) so that only the other
+    // block's columns stay in registers.
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
       const T* src = W + int64_t((blk == 0 ? bj : bi) * B + g) * mr;
+      T a = 0;
 #pragma unroll
       for (int t = 0; t < RPL; ++t) {
         const int row = l + GL * t;
-        s_x[g * CAP + GL * t + l] = row < mr ? src[row] : T(0);
+        const T v = row < mr ? src[row] : T(0);
+        s_x[g * CAP + GL * t + l] = v;
+        a = fma(v, v, a);
       }
+      a = group_sum<GL>(a);
+      if (l == 0) s_n[g] = double(a);
       __syncthreads();
       for (int r = 0; r < B - 1; ++r) {
         if (g < B / 2) {
           int i, j;
           rr_pair(B, r, g, i, j);
-          T x[RPL], y[RPL];
+          T* xi = s_x + i * CAP + l;
+          T* xj = s_x + j * CAP + l;
+          T ga = 0;
 #pragma unroll
-          for (int t = 0; t < RPL; ++t) {
-            x[t] = s_x[i * CAP + GL * t + l];
-            y[t] = s_x[j * CAP + GL * t + l];
-          }
-          double c, s;
-          angle(x, y, c, s);
-          const T ct = T(c), st = T(s);
+          for (int t = 0; t < RPL; ++t) ga = fma(xi[GL * t], xj[GL * t], ga);
+          const double g64 = double(group_sum<GL>(ga));
+          double al = s_n[i], be = s_n[j], c, sn, tt;
+          const int f = rotation_t(al, be, g64, tol, c, sn, tt);
+          nrot += f == 1;
+          bad |= f == 2;
+          if (f == 1) {
+            const T ct = T(c), st = T(sn);
 #pragma unroll
-          for (int t = 0; t < RPL; ++t) {
-            s_x[i * CAP + GL * t + l] = ct * x[t] - st * y[t];
-            s_x[j * CAP + GL * t + l] = st * x[t] + ct * y[t];
+            for (int t = 0; t < RPL; ++t) {
+              const T x = xi[GL * t], y = xj[GL * t];
+              xi[GL * t] = ct * x - st * y;
+              xj[GL * t] = st * x + ct * y;
+            }
+            if (l == 0) {
+              s_n[i] = fma(-tt, g64, al);
+              s_n[j] = fma(tt, g64, be);
+            }
           }
         }
         __syncthreads();
@@ -468,6 +492,10 @@ __global__ __launch_bounds__(kBjThreads) void bj_round_kernel(T* __restrict__ wb
         else
           top[t] = s_x[g * CAP + GL * t + l];
       }
+      if (blk == 0)
+        nbot = s_n[g];
+      else
+        ntop = s_n[g];
       __syncthreads();
     }
   } else {
@@ -479,13 +507,15 @@ __global__ __launch_bounds__(kBjThreads) void bj_round_kernel(T* __restrict__ wb
       top[t] = row < mr ? ti[row] : T(0);
       bot[t] = row < mr ? tj[row] : T(0);
     }
+    ntop = norm2(top);
+    nbot = norm2(bot);
   }
 
   // Cross pairs: group g holds column g of block bi and, in sub-round t,
-  // column (g + t) mod B of block bj.
+  // column (g + t) mod B of block bj, which carries its squared norm along.
   for (int sub = 0; sub < B; ++sub) {
     double c, s;
-    angle(top, bot, c, s);
+    angle(top, bot, ntop, nbot, c, s);
     const T ct = T(c), st = T(s);
 #pragma unroll
     for (int t = 0; t < RPL; ++t) {
@@ -496,10 +526,12 @@ __global__ __launch_bounds__(kBjThreads) void bj_round_kernel(T* __restrict__ wb
     if (sub + 1 < B) {
 #pragma unroll
       for (int t = 0; t < RPL; ++t) s_x[g * CAP + GL * t + l] = bot[t];
+      if (l == 0) s_n[g] = nbot;
       __syncthreads();
       const int from = (g + 1) % B;
 #pragma unroll
       for (int t = 0; t < RPL; ++t) bot[t] = s_x[from * CAP + GL * t + l];
+      nbot = s_n[from];
       __syncthreads();
     }
   }
