@@ -6,13 +6,16 @@
 // rows and nc = min(n1, n2) columns (the slice itself when n1 >= n2, its
 // transpose otherwise).  A sweep visits every column pair once, as a
 // round-robin tournament: nc_pad - 1 rounds of nc_pad / 2 disjoint pairs.  For
-// each pair, alpha = |w_i|^2, beta = |w_j|^2 and gamma = w_i.w_j are summed in
-// the data type (FP32 lane partials and FP32 cross-lane sums for FP32 data,
-// FP64 throughout for FP64 data; FP64 sums of FP32 data measured 1.6x slower
-// for the same sweeps and errors), and when |gamma| > tol * sqrt(alpha * beta)
-// (tol = sqrt(mr) * unit roundoff of the data type) the rotation parameters
-// are computed in FP64 and the rotation is applied to columns i, j of W in
-// the data type.  A slice has converged after a sweep without rotation.
+// each pair gamma = w_i.w_j is summed in the data type (FP32 lane partials and
+// FP32 cross-lane sums for FP32 data, FP64 throughout for FP64 data; FP64 sums
+// of FP32 data measured 1.6x slower for the same sweeps and errors); the
+// squared norms alpha = |w_i|^2, beta = |w_j|^2 are summed the same way when a
+// sweep (register kernel) or a launch (block kernel) starts and then carried
+// with the columns through the rotations (alpha - t gamma, beta + t gamma).
+// When |gamma| > tol * sqrt(alpha * beta) (tol = sqrt(mr) * unit roundoff of
+// the data type) the rotation parameters are computed in FP64 and the
+// rotation is applied to columns i, j of W in the data type.  A slice has
+// converged after a sweep without rotation.
 //
 // Register-resident kernel (the columns of a slice fit the registers of one
 // workgroup): 32 units of 16 lanes each hold J tournament slots (a top and a
