@@ -402,8 +402,11 @@ __global__ __launch_bounds__(kBjThreads) void bj_round_kernel(T* __restrict__ wb
                                                               double tol) {
   constexpr int GL = kBjThreads / B;  // lanes per group
   constexpr int CAP = GL * RPL;       // rows per column slot
-  __shared__ T s_x[B * CAP];
-  __shared__ double s_n[B];  // squared norms of the columns in the LDS slots
+  // Two exchange buffers (one barrier per cross sub-round) where they take
+  // at most 40 KiB; otherwise one buffer and two barriers.
+  constexpr bool kTwo = 2 * B * CAP * int(sizeof(T)) <= 40 * 1024;
+  __shared__ T s_x[(kTwo ? 2 : 1) * B * CAP];
+  __shared__ double s_n[(kTwo ? 2 : 1) * B];  // squared norms of the columns in the LDS slots
   const int slice = blockIdx.y;
   if (ctl[slice].state != 0 || !ctl[slice].live) return;
   int bi, bj;
@@ -527,15 +530,21 @@ __global__ __launch_bounds__(kBjThreads) void bj_round_kernel(T* __restrict__ wb
       bot[t] = st * x + ct * y;
     }
     if (sub + 1 < B) {
+      // With two buffers, sub-round t writes buffer t mod 2: a group writes it
+      // again only after the barrier of sub-round t + 1, which every group
+      // reaches after its reads of sub-round t.
+      const int half = kTwo ? (sub & 1) : 0;
+      T* xb = s_x + half * B * CAP;
+      double* nb = s_n + half * B;
 #pragma unroll
-      for (int t = 0; t < RPL; ++t) s_x[g * CAP + GL * t + l] = bot[t];
-      if (l == 0) s_n[g] = nbot;
+      for (int t = 0; t < RPL; ++t) xb[g * CAP + GL * t + l] = bot[t];
+      if (l == 0) nb[g] = nbot;
       __syncthreads();
       const int from = (g + 1) % B;
 #pragma unroll
-      for (int t = 0; t < RPL; ++t) bot[t] = s_x[from * CAP + GL * t + l];
-      nbot = s_n[from];
-      __syncthreads();
+      for (int t = 0; t < RPL; ++t) bot[t] = xb[from * CAP + GL * t + l];
+      nbot = nb[from];
+      if (!kTwo) __syncthreads();
     }
   }
   T* di = W + int64_t(bi * B + g) * mr;
