@@ -443,35 +443,45 @@ __global__ __launch_bounds__(kBjThreads) void bj_round_kernel(T* __restrict__ wb
   T top[RPL], bot[RPL];
   double ntop, nbot;
   if (round == 0) {
-    // Pairs inside each block, J first then I: columns in LDS slots, B / 2
-    // groups rotate one pair each per sub-round, streaming the two columns
-    // from LDS (once for gamma, once more to rotate) so that only the other
-    // block's columns stay in registers.
+    // Pairs inside each block: columns in LDS slots, B / 2 groups per block
+    // rotate one pair each per sub-round, streaming the two columns from LDS
+    // (once for gamma, once more to rotate) so that only the other block's
+    // columns stay in registers.  With two buffers both blocks run side by
+    // side (groups B / 2 .. B - 1 take block I), otherwise J first, then I.
+    constexpr int kPar = kTwo ? 2 : 1;
 #pragma unroll
-    for (int blk = 0; blk < 2; ++blk) {
-      const T* src = W + int64_t((blk == 0 ? bj : bi) * B + g) * mr;
-      T a = 0;
+    for (int pass = 0; pass < 2 / kPar; ++pass) {
 #pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        const int row = l + GL * t;
-        const T v = row < mr ? src[row] : T(0);
-        s_x[g * CAP + GL * t + l] = v;
-        a = fma(v, v, a);
+      for (int h = 0; h < kPar; ++h) {
+        const int blk = pass * kPar + h;  // 0: block J, 1: block I
+        const T* src = W + int64_t((blk == 0 ? bj : bi) * B + g) * mr;
+        T* dst = s_x + h * B * CAP + g * CAP + l;
+        T a = 0;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int row = l + GL * t;
+          const T v = row < mr ? src[row] : T(0);
+          dst[GL * t] = v;
+          a = fma(v, v, a);
+        }
+        a = group_sum<GL>(a);
+        if (l == 0) s_n[h * B + g] = double(a);
       }
-      a = group_sum<GL>(a);
-      if (l == 0) s_n[g] = double(a);
       __syncthreads();
+      const int h = g / (B / 2);
       for (int r = 0; r < B - 1; ++r) {
-        if (g < B / 2) {
+        if (h < kPar) {
           int i, j;
-          rr_pair(B, r, g, i, j);
-          T* xi = s_x + i * CAP + l;
-          T* xj = s_x + j * CAP + l;
+          rr_pair(B, r, g % (B / 2), i, j);
+          T* xi = s_x + h * B * CAP + i * CAP + l;
+          T* xj = s_x + h * B * CAP + j * CAP + l;
+          double* ni = s_n + h * B + i;
+          double* nj = s_n + h * B + j;
           T ga = 0;
 #pragma unroll
           for (int t = 0; t < RPL; ++t) ga = fma(xi[GL * t], xj[GL * t], ga);
           const double g64 = double(group_sum<GL>(ga));
-          double al = s_n[i], be = s_n[j], c, sn, tt;
+          double al = *ni, be = *nj, c, sn, tt;
           const int f = rotation_t(al, be, g64, tol, c, sn, tt);
           nrot += f == 1;
           bad |= f == 2;
@@ -484,24 +494,29 @@ __global__ __launch_bounds__(kBjThreads) void bj_round_kernel(T* __restrict__ wb
               xj[GL * t] = st * x + ct * y;
             }
             if (l == 0) {
-              s_n[i] = fma(-tt, g64, al);
-              s_n[j] = fma(tt, g64, be);
+              *ni = fma(-tt, g64, al);
+              *nj = fma(tt, g64, be);
             }
           }
         }
         __syncthreads();
       }
 #pragma unroll
-      for (int t = 0; t < RPL; ++t) {
+      for (int hh = 0; hh < kPar; ++hh) {
+        const int blk = pass * kPar + hh;
+        const T* src = s_x + hh * B * CAP + g * CAP + l;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          if (blk == 0)
+            bot[t] = src[GL * t];
+          else
+            top[t] = src[GL * t];
+        }
         if (blk == 0)
-          bot[t] = s_x[g * CAP + GL * t + l];
+          nbot = s_n[hh * B + g];
         else
-          top[t] = s_x[g * CAP + GL * t + l];
+          ntop = s_n[hh * B + g];
       }
-      if (blk == 0)
-        nbot = s_n[g];
-      else
-        ntop = s_n[g];
       __syncthreads();
     }
   } else {
