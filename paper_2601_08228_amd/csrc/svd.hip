@@ -143,6 +143,111 @@ __device__ __forceinline__ int rotation_t(double al, double be, double ga, doubl
   return 1;
 }
 
+// Ranks the nc columns by a strict total order: larger sigma first, NaN after
+// every number, ties (and NaNs) by column index; the ranks are therefore a
+// permutation.  s_order[rank] = column, and s_rank[column] = rank when s_rank
+// is given.  Called by every thread of the workgroup.
+__device__ void rank_columns(int nc, const double* s_sigma, int* s_order, int* s_rank) {
+  for (int c = threadIdx.x; c < nc; c += kJacobiThreads) {
+    const double sc = s_sigma[c];
+    const bool nan_c = sc != sc;
+    int rank = 0;
+    for (int o = 0; o < nc; ++o) {
+      const double so = s_sigma[o];
+      const bool nan_o = so != so;
+      const bool before = nan_o ? (nan_c && o < c)
+                                : (nan_c || so > sc || (so == sc && o < c));
+      rank += before;
+    }
+    s_order[rank] = c;
+    if (s_rank != nullptr) s_rank[c] = rank;
+  }
+}
+
+// emit_factors for the register-resident kernel, from the columns still in
+// registers (unit of 16 lanes, rows lane16 + 16 t; column ids ct[j], cb[j] of
+// the J top and bottom slots, nc for none), after rank_columns.  The k
+// leading columns go to LDS as they are (`cap` values at s_col, as many
+// columns at a time as fit; their signs at s_sgn), then are normalised (and
+// sign-fixed when they form U) in FP64 while written out row by row.
+template <typename T, int J, int RPL>
+__device__ __forceinline__ void emit_from_registers(const T (&tc)[J][RPL], const T (&bc)[J][RPL],
+                                    const int (&ct)[J], const int (&cb)[J], const SvdDims& d,
+                                    int slice, int lane16, const double* s_sigma,
+                                    const int* s_order, const int* s_rank, int* s_sgn, T* s_col,
+                                    int cap, T* __restrict__ uhat, T* __restrict__ shat,
+                                    T* __restrict__ vhat, T* __restrict__ us) {
+  const int mr = d.mr, nc = d.nc, k = d.k;
+  T* U = uhat + int64_t(slice) * d.n1 * k;
+  T* Vo = vhat + int64_t(slice) * d.n2 * k;
+  T* Us = us + int64_t(slice) * d.n1 * k;
+  const int per = cap / mr;  // columns staged at a time
+  for (int i0 = 0; i0 < k; i0 += per) {
+    const int i1 = i0 + per < k ? i0 + per : k;
+    auto stage = [&](const T (&x)[RPL], int c) {
+      if (c >= nc) return;
+      const int i = s_rank[c];
+      if (i < i0 || i >= i1) return;
+      // Largest |entry|, lowest row on ties: its sign is the column's (U is
+      // made positive there; w / sigma orders its entries as w does).
+      T best = T(-1);
+      int brow = 0x7fffffff, neg = 0;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int row = lane16 + 16 * t;
+        if (row < mr && fabs(x[t]) > best) {
+          best = fabs(x[t]);
+          brow = row;
+          neg = x[t] < T(0);
+        }
+      }
+#pragma unroll
+      for (int o = 8; o >= 1; o >>= 1) {
+        const T ob = __shfl_xor(best, o, 16);
+        const int orow = __shfl_xor(brow, o, 16);
+        const int on = __shfl_xor(neg, o, 16);
+        if (ob > best || (ob == best && orow < brow)) {
+          best = ob;
+          brow = orow;
+          neg = on;
+        }
+      }
+      T* col = s_col + (i - i0) * mr;
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int row = lane16 + 16 * t;
+        if (row < mr) col[row] = x[t];
+      }
+      if (lane16 == 0) {
+        s_sgn[i - i0] = neg;
+        shat[int64_t(slice) * k + i] = T(s_sigma[c]);
+      }
+    };
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      stage(tc[j], ct[j]);
+      stage(bc[j], cb[j]);
+    }
+    __syncthreads();
+    const int w = i1 - i0;
+    for (int e = threadIdx.x; e < mr * w; e += kJacobiThreads) {
+      const int row = e / w, ii = e - row * w;
+      const double sg = s_sigma[s_order[i0 + ii]];
+      const double inv = sg > 0 ? 1.0 / sg : 0.0;
+      const double v = double(s_col[ii * mr + row]) * inv;
+      if (d.trans) {
+        // W holds the transposed slice: w_c / sigma is a right singular vector.
+        Vo[int64_t(row) * k + i0 + ii] = T(v);
+      } else {
+        const double x = s_sgn[ii] && sg > 0 ? -v : v;
+        U[int64_t(row) * k + i0 + ii] = T(x);
+        Us[int64_t(row) * k + i0 + ii] = T(T(x) * T(sg));
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Singular values, ranking and the k leading columns of the factor formed by
 // W (column c at W + c * mr), called by every thread of the workgroup: U (and
 // U * sigma) when n1 >= n2, vhat otherwise.  The other factor is recovered
@@ -165,21 +270,7 @@ __device__ void emit_factors(const T* __restrict__ W, const SvdDims& d, int slic
     if (lane == 0) s_sigma[c] = sqrt(acc);
   }
   __syncthreads();
-  // Rank by a strict total order: larger sigma first, NaN after every number,
-  // ties (and NaNs) by column index; the ranks are therefore a permutation.
-  for (int c = threadIdx.x; c < nc; c += kJacobiThreads) {
-    const double sc = s_sigma[c];
-    const bool nan_c = sc != sc;
-    int rank = 0;
-    for (int o = 0; o < nc; ++o) {
-      const double so = s_sigma[o];
-      const bool nan_o = so != so;
-      const bool before = nan_o ? (nan_c && o < c)
-                                : (nan_c || so > sc || (so == sc && o < c));
-      rank += before;
-    }
-    s_order[rank] = c;
-  }
+  rank_columns(nc, s_sigma, s_order, nullptr);
   __syncthreads();
 
   const int k = d.k;
@@ -962,26 +1053,46 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
     }
   }
   rescale(false);  // the columns of W themselves
-
+  // The factors are formed from the registers: W never goes to memory.  The
+  // norms, scales and exchange buffers are free from here on (s_sigma holds
+  // the singular values, s_x the ranks and the staged output columns).
+  __syncthreads();
+  // After sw sweeps the circle has advanced sw * 2H = sw (mod CIRC) positions.
+  const int rf = sw % CIRC;
   if (active) {
-    // After sw sweeps the circle has advanced sw * 2H = sw (mod CIRC) positions.
-    const int r = sw % CIRC;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      const int cti = top_id(q0 + j, r), cbi = bot_id(q0 + j, r);
+      double pt = 0, pb = 0;
 #pragma unroll
       for (int t = 0; t < RPL; ++t) {
-        const int row = lane16 + 16 * t;
-        if (row < mr) {
-          if (cti < nc) W[cti * mr + row] = tc[j][t];
-          if (cbi < nc) W[cbi * mr + row] = bc[j][t];
-        }
+        pt = fma(double(tc[j][t]), double(tc[j][t]), pt);
+        pb = fma(double(bc[j][t]), double(bc[j][t]), pb);
+      }
+      pt = row_sum16(pt);
+      pb = row_sum16(pb);
+      const int cti = top_id(q0 + j, rf), cbi = bot_id(q0 + j, rf);
+      if (lane16 == 0) {
+        if (cti < nc) s_sigma[cti] = sqrt(pt);
+        if (cbi < nc) s_sigma[cbi] = sqrt(pb);
       }
     }
   }
   __syncthreads();
-  emit_factors<T>(W, d, slice, uhat, shat, vhat, us, s_sigma,
-                  s_order);
+  constexpr int kOrd = int(sizeof(s_order) / sizeof(int));
+  int* const s_rank = reinterpret_cast<int*>(&s_x[0][0][0][0]);
+  rank_columns(nc, s_sigma, s_order, s_rank);
+  __syncthreads();
+  int cti[J], cbi[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    cti[j] = active ? top_id(q0 + j, rf) : nc;
+    cbi[j] = active ? bot_id(q0 + j, rf) : nc;
+  }
+  // In s_x: ranks (kOrd ints), signs (kOrd ints), then the staged columns.
+  emit_from_registers<T, J, RPL>(tc, bc, cti, cbi, d, slice, lane16, s_sigma, s_order, s_rank,
+                                 s_rank + kOrd, reinterpret_cast<T*>(s_rank + 2 * kOrd),
+                                 int((sizeof(s_x) - 2 * kOrd * sizeof(int)) / sizeof(T)), uhat,
+                                 shat, vhat, us);
   if (threadIdx.x == 0) info[slice] = converged ? sw : -sw;
 }
 
