@@ -748,9 +748,8 @@ constexpr int kRescaleBlocks = 16;
 // bottom column into top slot 1.
 template <typename T, int J, int RPL>
 __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
-    const T* __restrict__ ah, T* __restrict__ wbuf, SvdDims d, int nunits, int max_sweeps,
-    T* __restrict__ uhat, T* __restrict__ shat, T* __restrict__ vhat, T* __restrict__ us,
-    int32_t* __restrict__ info) {
+    const T* __restrict__ ah, SvdDims d, int nunits, int max_sweeps, T* __restrict__ uhat,
+    T* __restrict__ shat, T* __restrict__ vhat, T* __restrict__ us, int32_t* __restrict__ info) {
   static_assert(J == 1 || J == 2 || J == 4, "J is 1, 2 or 4");
   constexpr int M = J - 1;
   constexpr int SLOT = 16 * RPL + 16;  // padding puts the 4 units of a wave on other banks
@@ -765,7 +764,6 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
   const int last = nunits - 1;
   const int q0 = unit * J;
   const T* a = ah + int64_t(slice) * d.n1 * d.n2;
-  T* W = wbuf + int64_t(slice) * nc * mr;
 
   // [round parity][outgoing top, outgoing bottom][unit][row]
   __shared__ T s_x[2][2][kUnits][SLOT];
@@ -1632,7 +1630,8 @@ inline SvdPlan plan_svd(int64_t n1, int64_t n2, int64_t p, int64_t nsl, int k, s
   const int64_t mr = n1 > n2 ? n1 : n2;
   const int64_t nc = n1 > n2 ? n2 : n1;
   const JacobiChoice jc = choose_jacobi(int(mr), int(nc), es, nsl);
-  const int64_t ncw = jc.reg ? nc : int64_t(jc.bj.nbp) * jc.bj.B;  // columns of W
+  // Columns of W in memory: the register kernel keeps W in registers.
+  const int64_t ncw = jc.reg ? 0 : int64_t(jc.bj.nbp) * jc.bj.B;
   SvdPlan pl{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -1711,7 +1710,7 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
     const int J = jc.J, rpl = jc.rpl, nunits = jc.nunits;
 #define WP_JREG(JJ, RR)                                                                        \
   if (J == JJ && rpl == RR)                                                                    \
-    hipLaunchKernelGGL((jacobi_reg_kernel<T, JJ, RR>), grid, block, 0, s, ah, w, d, nunits,     \
+    hipLaunchKernelGGL((jacobi_reg_kernel<T, JJ, RR>), grid, block, 0, s, ah, d, nunits,        \
                        max_sweeps, uhat, shat, vhat, us, info);
     WP_JREG(1, 1) WP_JREG(1, 2) WP_JREG(1, 4) WP_JREG(1, 8)
     WP_JREG(2, 1) WP_JREG(2, 2) WP_JREG(2, 4) WP_JREG(2, 8)
