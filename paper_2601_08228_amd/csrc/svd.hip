@@ -181,7 +181,10 @@ __device__ __forceinline__ void emit_from_registers(const T (&tc)[J][RPL], const
   T* U = uhat + int64_t(slice) * d.n1 * k;
   T* Vo = vhat + int64_t(slice) * d.n2 * k;
   T* Us = us + int64_t(slice) * d.n1 * k;
-  const int per = cap / mr;  // columns staged at a time
+  // Columns staged at a time: the exchange buffers hold 4 kUnits slots of
+  // 16 RPL + 16 >= mr + 16 values, so at least 128 columns fit next to the
+  // rank and sign arrays.
+  const int per = cap / mr;
   for (int i0 = 0; i0 < k; i0 += per) {
     const int i1 = i0 + per < k ? i0 + per : k;
     auto stage = [&](const T (&x)[RPL], int c) {
@@ -884,9 +887,12 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
   // A sweep runs 2H = CIRC + 1 rounds, a whole number of J-round blocks, so
   // the register renaming is the identity at every sweep end (the extra
   // round repeats the pairs of the sweep's first round).
-  // Lane j of a unit (j < J) keeps the norms and scales of the unit's pair j:
-  // top position q0 + j and the bottom position below it.
-  const int jl = lane16 & M;
+  // The 16 / J lanes j (16 / J) .. of a unit evaluate the angle of the unit's
+  // pair j (top position q0 + j and the bottom position below it); the first
+  // of them writes its norms and scales.
+  constexpr int G = 16 / J;
+  const int jl = lane16 / G;
+  const bool lead = (lane16 & (G - 1)) == 0;
   int rc = 0;  // rounds since the start, mod CIRC (the circle's position)
   // Folds each scale into its column (w = d x), sets d = e = 1 and, at a
   // sweep's start, sums the exact squared norms; at a multiple of J rounds the
@@ -935,33 +941,52 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
       static_for<0, J>([&](auto RR) {
         constexpr int rr = decltype(RR)::value;
         {
-          // gamma of the scaled columns x, y of each pair.
-          T ga[J];
+          // gamma of the scaled columns x, y of each pair: the J lane partials
+          // are summed over the row by a transposing reduction that leaves
+          // pair j's sum in lanes j (16 / J) ..: across the row mirror (lanes
+          // with bit 3 clear keep pairs 0, 1 and pass 2, 3), then the half
+          // mirror (bit 2), then inside quads; the lanes of a quad end with
+          // the same bits.
+          T pg[J];
 #pragma unroll
           for (int j = 0; j < J; ++j) {
             const T* x = tc[(j - rr) & M];
             const T* y = bc[(j + rr) & M];
-            T pg = 0;
+            T a = 0;
 #pragma unroll
-            for (int t = 0; t < RPL; ++t) pg = fma(x[t], y[t], pg);
-            ga[j] = row_sum16(pg);
+            for (int t = 0; t < RPL; ++t) a = fma(x[t], y[t], a);
+            pg[j] = a;
           }
-          // Pair j in lane j: w_i = d_i x_i, w_j = d_j x_j, so the inner
-          // product of the columns is d_i d_j (x_i . x_j); alpha and beta
-          // are the carried squared norms of w_i, w_j.
+          T sg;
+          if constexpr (J == 4) {
+            const bool b3 = (lane16 & 8) != 0, b2 = (lane16 & 4) != 0;
+            const T k0 = b3 ? pg[2] : pg[0], s0 = b3 ? pg[0] : pg[2];
+            const T k1 = b3 ? pg[3] : pg[1], s1 = b3 ? pg[1] : pg[3];
+            const T h0 = k0 + dpp_move<0x140>(s0);  // row_mirror
+            const T h1 = k1 + dpp_move<0x140>(s1);
+            sg = (b2 ? h1 : h0) + dpp_move<0x141>(b2 ? h0 : h1);  // row_half_mirror
+          } else if constexpr (J == 2) {
+            const bool b3 = (lane16 & 8) != 0;
+            sg = (b3 ? pg[1] : pg[0]) + dpp_move<0x140>(b3 ? pg[0] : pg[1]);
+            sg += dpp_move<0x141>(sg);
+          } else {
+            sg = pg[0] + dpp_move<0x140>(pg[0]);
+            sg += dpp_move<0x141>(sg);
+          }
+          sg += dpp_move<0x4e>(sg);  // quad_perm [2,3,0,1]
+          sg += dpp_move<0xb1>(sg);  // quad_perm [1,0,3,2]
+          // w_i = d_i x_i, w_j = d_j x_j, so the inner product of the
+          // columns is d_i d_j (x_i . x_j); alpha and beta are the carried
+          // squared norms of w_i, w_j.
           const int id_t = active ? top_id(q0 + jl, rc) : 0;
           const int id_b = active ? bot_id(q0 + jl, rc) : 0;
           const double al = double(s_norm[id_t]), be = double(s_norm[id_b]);
           const double di = s_d[id_t], dj = s_d[id_b];
           const double ei = s_e[id_t], ej = s_e[id_b];
-          T sg = ga[0];
-#pragma unroll
-          for (int j = 1; j < J; ++j)
-            if (lane16 == j) sg = ga[j];
           const double gam = double(sg) * di * dj;
           double cd, sd, td;
           const int flag = rotation_t(al, be, gam, tol, cd, sd, td);
-          if (lane16 < J) {
+          if (lead) {
             my_rot += flag == 1;
             my_bad |= flag == 2;
           }
@@ -975,7 +1000,7 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
           const double ic = cd * fma(td, td, 1.0);
           const T fb = T(td * di * ej);
           const T fa = T(td * dj * ei * cd * cd);
-          if (active && lane16 < J && flag == 1) {
+          if (active && lead && flag == 1) {
             s_norm[id_t] = T(fma(-td, gam, al));
             s_norm[id_b] = T(fma(td, gam, be));
             s_d[id_t] = ic * di;
@@ -985,7 +1010,7 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
           }
           static_for<0, J>([&](auto JJ) {
             constexpr int j = decltype(JJ)::value;
-            const T ax = row_bcast<j>(fa), bx = row_bcast<j>(fb);
+            const T ax = row_bcast<j * G>(fa), bx = row_bcast<j * G>(fb);
             T* x = tc[(j - rr) & M];
             T* y = bc[(j + rr) & M];
 #pragma unroll
