@@ -1142,10 +1142,13 @@ __global__ __launch_bounds__(256) void recover_kernel(const T* __restrict__ ah, 
   const T* src = d.trans ? Vo : U;  // the columns formed from W, mr entries
   T* dst = d.trans ? U : Vo;        // the columns recovered here, nc entries
   constexpr int kOut = kMaxSide / 256;
-  __shared__ double s_src[kRecCols][kMaxSide];
-  __shared__ double s_best[kRecCols][256];
-  __shared__ int s_row[kRecCols][256];
-  __shared__ double s_val[kRecCols][256];
+  // Dynamic LDS, sized by the launch: the kRecCols source columns (mr values
+  // each), then (transposed slices only) the sign search of every column.
+  extern __shared__ double s_dyn[];
+  double* const s_src = s_dyn;  // [kRecCols][mr]
+  double* const s_best = s_dyn + kRecCols * mr;  // [kRecCols][256]
+  double* const s_val = s_best + kRecCols * 256;  // [kRecCols][256]
+  int* const s_row = reinterpret_cast<int*>(s_val + kRecCols * 256);  // [kRecCols][256]
   // Columns of singular values at or below the numerical rank cut
   // max(n1, n2) u sigma_1 (the cut of the pseudo-inverse) are not recovered
   // (zero): A^T u_i / sigma_i would amplify the rounding of u_i beyond one.
@@ -1160,7 +1163,7 @@ __global__ __launch_bounds__(256) void recover_kernel(const T* __restrict__ ah, 
   for (int t = threadIdx.x; t < mr; t += 256)
 #pragma unroll
     for (int c = 0; c < kRecCols; ++c)
-      s_src[c][t] = i0 + c < k ? double(src[int64_t(t) * k + i0 + c]) : 0.0;
+      s_src[c * mr + t] = i0 + c < k ? double(src[int64_t(t) * k + i0 + c]) : 0.0;
   __syncthreads();
   double out[kOut][kRecCols];
   double best[kRecCols], bval[kRecCols];
@@ -1181,13 +1184,13 @@ __global__ __launch_bounds__(256) void recover_kernel(const T* __restrict__ ah, 
         for (int t = 0; t < mr; ++t) {
           const double a = double(A[int64_t(r) * d.n2 + t]);
 #pragma unroll
-          for (int c = 0; c < kRecCols; ++c) acc[c] = fma(a, s_src[c][t], acc[c]);
+          for (int c = 0; c < kRecCols; ++c) acc[c] = fma(a, s_src[c * mr + t], acc[c]);
         }
       else
         for (int t = 0; t < mr; ++t) {
           const double a = double(A[int64_t(t) * d.n2 + r]);
 #pragma unroll
-          for (int c = 0; c < kRecCols; ++c) acc[c] = fma(a, s_src[c][t], acc[c]);
+          for (int c = 0; c < kRecCols; ++c) acc[c] = fma(a, s_src[c * mr + t], acc[c]);
         }
 #pragma unroll
       for (int c = 0; c < kRecCols; ++c) {
@@ -1209,27 +1212,28 @@ __global__ __launch_bounds__(256) void recover_kernel(const T* __restrict__ ah, 
     // Largest |U| entry over each column, lowest row on ties.
 #pragma unroll
     for (int c = 0; c < kRecCols; ++c) {
-      s_best[c][threadIdx.x] = best[c];
-      s_row[c][threadIdx.x] = brow[c];
-      s_val[c][threadIdx.x] = bval[c];
+      s_best[c * 256 + threadIdx.x] = best[c];
+      s_row[c * 256 + threadIdx.x] = brow[c];
+      s_val[c * 256 + threadIdx.x] = bval[c];
     }
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
       if (threadIdx.x < w) {
         const int o = threadIdx.x + w;
 #pragma unroll
-        for (int c = 0; c < kRecCols; ++c)
-          if (s_best[c][o] > s_best[c][threadIdx.x] ||
-              (s_best[c][o] == s_best[c][threadIdx.x] && s_row[c][o] < s_row[c][threadIdx.x])) {
-            s_best[c][threadIdx.x] = s_best[c][o];
-            s_row[c][threadIdx.x] = s_row[c][o];
-            s_val[c][threadIdx.x] = s_val[c][o];
+        for (int c = 0; c < kRecCols; ++c) {
+          const int me = c * 256 + threadIdx.x, ot = c * 256 + o;
+          if (s_best[ot] > s_best[me] || (s_best[ot] == s_best[me] && s_row[ot] < s_row[me])) {
+            s_best[me] = s_best[ot];
+            s_row[me] = s_row[ot];
+            s_val[me] = s_val[ot];
           }
+        }
       }
       __syncthreads();
     }
 #pragma unroll
-    for (int c = 0; c < kRecCols; ++c) sgn[c] = s_val[c][0] < 0 ? -1.0 : 1.0;
+    for (int c = 0; c < kRecCols; ++c) sgn[c] = s_val[c * 256] < 0 ? -1.0 : 1.0;
   }
 #pragma unroll
   for (int j = 0; j < kOut; ++j) {
@@ -1247,7 +1251,7 @@ __global__ __launch_bounds__(256) void recover_kernel(const T* __restrict__ ah, 
 #pragma unroll
     for (int c = 0; c < kRecCols; ++c)
       if (i0 + c < k && sgn[c] < 0)
-        for (int t = threadIdx.x; t < mr; t += 256) Vo[int64_t(t) * k + i0 + c] = T(-s_src[c][t]);
+        for (int t = threadIdx.x; t < mr; t += 256) Vo[int64_t(t) * k + i0 + c] = T(-s_src[c * mr + t]);
 }
 
 // Gram matrix G = X^T X (FP64) of one slice X (n x k row-major, k <= 64) for
@@ -1783,9 +1787,19 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
   e = hipGetLastError();
   if (e == hipSuccess && ev_end != nullptr) e = hipEventRecord(ev_end, s);
   if (e != hipSuccess || !second_factor) return e;
-  hipLaunchKernelGGL((recover_kernel<T>),
-                     dim3(unsigned(nsl), unsigned((k + kRecCols - 1) / kRecCols)), dim3(256), 0, s,
-                     ah, d, uhat, shat, vhat, us);
+  {
+    // LDS sized to the slice (not to the largest one): more workgroups per CU.
+    const size_t lds = size_t(kRecCols) * d.mr * sizeof(double) +
+                       (d.trans ? size_t(kRecCols) * 256 * (2 * sizeof(double) + sizeof(int)) : 0);
+    if (lds > 65536) {
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(recover_kernel<T>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((recover_kernel<T>),
+                       dim3(unsigned(nsl), unsigned((k + kRecCols - 1) / kRecCols)), dim3(256), lds,
+                       s, ah, d, uhat, shat, vhat, us);
+  }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
 
