@@ -1102,6 +1102,8 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
   }
   __syncthreads();
   constexpr int kOrd = int(sizeof(s_order) / sizeof(int));
+  static_assert(sizeof(s_x) >= 2 * kOrd * sizeof(int) + 128 * 16 * RPL * sizeof(T),
+                "the exchange buffers stage at least 128 columns of 16 RPL rows");
   int* const s_rank = reinterpret_cast<int*>(&s_x[0][0][0][0]);
   rank_columns(nc, s_sigma, s_order, s_rank);
   __syncthreads();
