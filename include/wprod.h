@@ -227,7 +227,9 @@ size_t w_product_noalloc_scratch_bytes(void);
  * Truncated SVD of every coefficient slice of W(A), A (p, n1, n2), by one-sided
  * Jacobi.  Precision: the rotation parameters (cosine and sine, from the
  * tangent of the angle that zeroes the pair's inner product) are computed in
- * FP64; the column norms and the inner product they come from are accumulated
+ * FP64 (to about one unit in the last place for WP_F64, to ~4e-15 relative for
+ * WP_F32, whose rotations are applied in FP32); the column norms and the inner
+ * product they come from are accumulated
  * in the data type (FP32 sums of FP32 products for WP_F32, FP64 for WP_F64);
  * the rotations are applied to the data in `dtype`.  The pair threshold is
  * |w_i.w_j| > sqrt(max(n1, n2)) * u * |w_i| |w_j| (u = 2^-24 for F32, 2^-53 for

@@ -83,49 +83,46 @@ struct SvdDims {
 };
 
 // FP64 reciprocal and reciprocal square root from the hardware estimates
-// (v_rcp_f64 / v_rsq_f64) refined by two Newton steps each: accurate to a few
-// units in the last place, without the scaling and fix-up sequences of the
-// correctly rounded library routines.  Arguments are finite and positive.
+// (v_rcp_f64 / v_rsq_f64, ~5e-8 relative) refined by NS Newton steps, each of
+// which doubles the number of correct bits: measured on gfx950 over 2^20
+// arguments, one step leaves 4e-15 (rsq) and 2e-15 (rcp), two 2.4e-16 and
+// 1.1e-16, about one unit in the last place; no scaling and fix-up sequences
+// as in the correctly rounded library routines.  Arguments are finite and
+// positive.
+template <int NS>
 __device__ __forceinline__ double rcp64(double x) {
   double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+  }
+  return r;
 }
+template <int NS>
 __device__ __forceinline__ double rsqrt64(double x) {
   double y = __builtin_amdgcn_rsq(x);
   const double hx = 0.5 * x;
-  y = y * fma(-hx * y, y, 1.5);
-  y = y * fma(-hx * y, y, 1.5);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) y = y * fma(-hx * y, y, 1.5);
   return y;
 }
 
-// Rotation that zeroes w_i.w_j, all in FP64.  With d = beta - alpha the
+// Newton steps of the rotation parameters for data of type T: FP64 data get
+// parameters accurate to the last place; for FP32 data, whose rotations are
+// applied in FP32, one step leaves them accurate to ~4e-15.
+template <typename T>
+constexpr int kRotNewton = sizeof(T) == 8 ? 2 : 1;
+
+// Rotation that zeroes w_i.w_j, evaluated in FP64.  With d = beta - alpha the
 // tangent t = sign(d) * 2 gamma / (|d| + sqrt(d^2 + 4 gamma^2)) is the smaller
 // root of t^2 + 2 zeta t - 1 = 0, zeta = d / (2 gamma) (Rutishauser's choice);
-// c = 1 / sqrt(1 + t^2), s = c t.
-// Returns 0: below the threshold (c = 1, s = 0), 1: rotate, 2: non-finite input.
-__device__ __forceinline__ int rotation(double al, double be, double ga, double tol, double& c,
-                                        double& s) {
-  c = 1.0;
-  s = 0.0;
-  if (!(isfinite(al) && isfinite(be) && isfinite(ga))) return 2;
-  if (!(ga * ga > tol * tol * (al * be))) return 0;
-  // Here gamma != 0, so q > 0 and every argument below is positive.
-  const double d = be - al;
-  const double g2 = 2.0 * ga;
-  const double q = fma(d, d, g2 * g2);
-  const double h = q * rsqrt64(q);
-  const double t = copysign(1.0, d) * g2 * rcp64(fabs(d) + h);
-  c = rsqrt64(fma(t, t, 1.0));
-  s = c * t;
-  return 1;
-}
-
-// rotation() that also returns the tangent t (0 below the threshold), for
-// updating the two column norms: with gamma zeroed, |w_i'|^2 = alpha - t gamma
-// and |w_j'|^2 = beta + t gamma.
+// c = 1 / sqrt(1 + t^2), s = c t.  The tangent is returned too, for updating
+// the two column norms: with gamma zeroed, |w_i'|^2 = alpha - t gamma and
+// |w_j'|^2 = beta + t gamma.
+// Returns 0: below the threshold (c = 1, s = t = 0), 1: rotate, 2: non-finite
+// input.
+template <int NS>
 __device__ __forceinline__ int rotation_t(double al, double be, double ga, double tol, double& c,
                                           double& s, double& t) {
   c = 1.0;
@@ -133,12 +130,13 @@ __device__ __forceinline__ int rotation_t(double al, double be, double ga, doubl
   t = 0.0;
   if (!(isfinite(al) && isfinite(be) && isfinite(ga))) return 2;
   if (!(ga * ga > tol * tol * (al * be))) return 0;
+  // Here gamma != 0, so q > 0 and every argument below is positive.
   const double d = be - al;
   const double g2 = 2.0 * ga;
   const double q = fma(d, d, g2 * g2);
-  const double h = q * rsqrt64(q);
-  t = copysign(1.0, d) * g2 * rcp64(fabs(d) + h);
-  c = rsqrt64(fma(t, t, 1.0));
+  const double h = q * rsqrt64<NS>(q);
+  t = copysign(1.0, d) * g2 * rcp64<NS>(fabs(d) + h);
+  c = rsqrt64<NS>(fma(t, t, 1.0));
   s = c * t;
   return 1;
 }
@@ -528,7 +526,7 @@ __global__ __launch_bounds__(kBjThreads) void bj_round_kernel(T* __restrict__ wb
     for (int t = 0; t < RPL; ++t) ga = fma(x[t], y[t], ga);
     const double g64 = double(group_sum<GL>(ga));
     double tt;
-    const int f = rotation_t(al, be, g64, tol, c, s, tt);
+    const int f = rotation_t<kRotNewton<T>>(al, be, g64, tol, c, s, tt);
     al = fma(-tt, g64, al);
     be = fma(tt, g64, be);
     nrot += f == 1;
@@ -577,7 +575,7 @@ __global__ __launch_bounds__(kBjThreads) void bj_round_kernel(T* __restrict__ wb
           for (int t = 0; t < RPL; ++t) ga = fma(xi[GL * t], xj[GL * t], ga);
           const double g64 = double(group_sum<GL>(ga));
           double al = *ni, be = *nj, c, sn, tt;
-          const int f = rotation_t(al, be, g64, tol, c, sn, tt);
+          const int f = rotation_t<kRotNewton<T>>(al, be, g64, tol, c, sn, tt);
           nrot += f == 1;
           bad |= f == 2;
           if (f == 1) {
@@ -985,7 +983,7 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
           const double ei = s_e[id_t], ej = s_e[id_b];
           const double gam = double(sg) * di * dj;
           double cd, sd, td;
-          const int flag = rotation_t(al, be, gam, tol, cd, sd, td);
+          const int flag = rotation_t<kRotNewton<T>>(al, be, gam, tol, cd, sd, td);
           if (lead) {
             my_rot += flag == 1;
             my_bad |= flag == 2;
