@@ -273,6 +273,26 @@ def test_register_kernel_staged_columns(wp, shape, dtype, k):
     assert host(res.orth_err).max() <= bars["orth"]
 
 
+# Register kernel with more leading columns than the freed exchange buffers
+# stage at once (k = 150 > 128 columns of 256 rows): the factors leave the
+# kernel in two chunks.  Both orientations (the second forms V from W).
+@pytest.mark.parametrize("shape", [(64, 256, 160), (64, 160, 256)])
+def test_register_kernel_chunked_factors(wp, shape):
+    import torch
+    p, n1, n2 = shape
+    k = 150
+    a = cast(_gapped(p, n1, n2, k, seed=17), np.float32)
+    res = wp.w_svd(to_dev(a, torch.float32), 0, k)
+    torch.cuda.synchronize()
+    assert host(res.info).min() > 0
+    _, sh_ref, _, ak_ref = orc.w_svd(a, 0, k)
+    bars = svd_bars(a, k, "f32", L=0)
+    assert rel_fro(host(res.shat), sh_ref) <= 1e-5
+    assert rel_fro(host(res.ak), ak_ref) <= 1e-5
+    assert host(res.orth_err).max() <= bars["orth"]
+    _check_factors(res, a, k, bars, "f32")
+
+
 # ---- sp-w-svd (Sec. IV-B): only s_L and d_L are decomposed ---------------------
 
 @pytest.mark.parametrize("shape,L,k", [((32, 20, 14), 3, 5), ((16, 7, 9), 4, 3),
