@@ -1570,14 +1570,20 @@ __global__ __launch_bounds__(256) void gram_dev_kernel(const double* __restrict_
 }
 
 // max |X^T X - I| over the k x k Gram matrix of one slice of X (n x k,
-// row-major, k <= 64), FP64, zero columns left out.
+// row-major, k <= 64), FP64, zero columns left out; both factors in one
+// launch (workgroups [0, nsl) take X0 = U, [nsl, 2 nsl) X1 = V), part[f nsl +
+// slice].
 template <typename T>
-__global__ __launch_bounds__(256) void orth_kernel(const T* __restrict__ x, int n, int k,
-                                                   double* __restrict__ part) {
+__global__ __launch_bounds__(256) void orth_kernel(const T* __restrict__ x0,
+                                                   const T* __restrict__ x1, int n0, int n1,
+                                                   int k, int nsl, double* __restrict__ part) {
   __shared__ double s_g[64 * 64];
   __shared__ double s_blk[kGramRows * 64];
   __shared__ double s_red[256];
-  const int slice = blockIdx.x;
+  const int f = int(blockIdx.x) >= nsl ? 1 : 0;
+  const int slice = int(blockIdx.x) - f * nsl;
+  const T* x = f ? x1 : x0;
+  const int n = f ? n1 : n0;
   double acc[16];
   gram_k64<T>(x + int64_t(slice) * n * k, n, k, acc, s_blk);
 #pragma unroll
@@ -1587,11 +1593,13 @@ __global__ __launch_bounds__(256) void orth_kernel(const T* __restrict__ x, int 
   }
   __syncthreads();
   const double dev = gram_dev(s_g, k, s_red);
-  if (threadIdx.x == 0) part[slice] = dev;
+  if (threadIdx.x == 0) part[blockIdx.x] = dev;
 }
 
+// out[b] = max over part[b n, (b + 1) n), NaN-propagating; one workgroup per b.
 __global__ __launch_bounds__(256) void max_reduce_kernel(const double* __restrict__ part, int64_t n,
                                                          double* __restrict__ out) {
+  part += int64_t(blockIdx.x) * n;
   double worst = 0;
   for (int64_t e = threadIdx.x; e < n; e += 256) {
     const double v = part[e];
@@ -1608,7 +1616,7 @@ __global__ __launch_bounds__(256) void max_reduce_kernel(const double* __restric
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = red[0];
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 // Which Jacobi kernel a call takes.  Register-resident kernel when the
@@ -1865,11 +1873,11 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
   if (orth_err != nullptr) {
     const T* fac[2] = {uhat, vhat};
     const int rows[2] = {int(n1), int(n2)};
-    for (int f = 0; f < 2; ++f) {
-      if (k <= 64) {
-        hipLaunchKernelGGL((orth_kernel<T>), dim3(unsigned(nsl)), dim3(256), 0, s, fac[f], rows[f],
-                           k, part + f * nsl);
-      } else {
+    if (k <= 64) {
+      hipLaunchKernelGGL((orth_kernel<T>), dim3(unsigned(2 * nsl)), dim3(256), 0, s, uhat, vhat,
+                         int(n1), int(n2), k, int(nsl), part);
+    } else {
+      for (int f = 0; f < 2; ++f) {
         const unsigned kt = unsigned((k + 63) / 64);
         const int64_t per = int64_t(rows[f]) * k;
         hipLaunchKernelGGL((small_gemm_kernel<T, T, double, true>), dim3(kt, kt, unsigned(nsl)),
@@ -1878,9 +1886,8 @@ hipError_t run_svd(const T* a, int64_t n1, int64_t n2, int64_t p, int L, int k, 
         hipLaunchKernelGGL(gram_dev_kernel, dim3(unsigned(nsl)), dim3(256), 0, s, gram, k,
                            part + f * nsl);
       }
-      hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, s, part + f * nsl, nsl,
-                         orth_err + f);
     }
+    hipLaunchKernelGGL(max_reduce_kernel, dim3(2), dim3(256), 0, s, part, nsl, orth_err);
     e = hipGetLastError();
   }
   return e;
