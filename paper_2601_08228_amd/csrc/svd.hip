@@ -729,14 +729,15 @@ constexpr int kRescaleBlocks = 16;
 // Per round and pair: gamma as a 16-lane row sum (FP32 data: FP32 lane
 // partials and FP32 row sums, at most RPL + 4 rounding steps; FP64 data: FP64
 // throughout); the two column norms alpha, beta are not summed again but
-// carried with the columns: each slot keeps its column's squared norm (the
-// same value in the unit's 16 lanes), summed exactly at the start of every
-// sweep and updated after each rotation by alpha - t gamma, beta + t gamma
-// (exact for the rotation that zeroes gamma).  That saves two of the three
-// dot products of a pair; the drift of the carried norms within one sweep
-// costs at most one sweep more on the hyperspectral-like test tensor.  The
-// J angles of a unit are evaluated together in FP64, pair j in lane j, and
-// the cosines, sines and updated norms are broadcast to the row.
+// carried with the columns: each column's squared norm is kept in FP64 (in
+// LDS, by column), summed exactly at the start of every sweep and updated
+// after each rotation by alpha - t gamma, beta + t gamma (exact for the
+// rotation that zeroes gamma).  That saves two of the three dot products of
+// a pair.  Kept in FP32 instead, the rounding of every update drifts the
+// norms enough within a sweep to cost the slowest slice of the
+// hyperspectral-like test tensor one more sweep.  The J angles of a unit are
+// evaluated together in FP64, pair j in lanes j (16 / J) .., and the shear
+// factors are broadcast to the row.
 //
 // Circle method: position 0 (unit 0, top slot 0) is fixed and the other
 // positions advance one step per round (top q -> top q+1, top H-1 -> bottom
@@ -773,16 +774,16 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
   __shared__ int s_bad;
   __shared__ double s_sigma[1024];
   __shared__ int s_order[1024];
-  // Squared norm of every column, indexed by column (the columns move
+  // Squared norm of every column (carried in FP64), indexed by column (the columns move
   // between units, their norms stay in place); shares the storage of the
   // singular values, which are formed only after the sweeps.
   // With them, the scales d of the columns (w = d x) and their inverses e,
   // indexed the same way.
   constexpr int kPos = 2 * kUnits * 4;
-  static_assert(kPos * (sizeof(T) + 2 * sizeof(double)) <= sizeof(s_sigma), "fits");
+  static_assert(kPos * 3 * sizeof(double) <= sizeof(s_sigma), "fits");
   double* const s_d = s_sigma;
   double* const s_e = s_sigma + kPos;
-  T* const s_norm = reinterpret_cast<T*>(s_sigma + 2 * kPos);
+  double* const s_norm = s_sigma + 2 * kPos;
 
   // Column held by slot q after r rounds (0 <= r < CIRC): position p starts
   // with column p and the circle advances one position per round.
@@ -919,8 +920,8 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
         s_d[ib] = 1.0;
         s_e[ib] = 1.0;
         if (norms) {
-          s_norm[it] = pa;
-          s_norm[ib] = pb;
+          s_norm[it] = double(pa);
+          s_norm[ib] = double(pb);
         }
       }
     }
@@ -978,7 +979,7 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
           // squared norms of w_i, w_j.
           const int id_t = active ? top_id(q0 + jl, rc) : 0;
           const int id_b = active ? bot_id(q0 + jl, rc) : 0;
-          const double al = double(s_norm[id_t]), be = double(s_norm[id_b]);
+          const double al = s_norm[id_t], be = s_norm[id_b];
           const double di = s_d[id_t], dj = s_d[id_b];
           const double ei = s_e[id_t], ej = s_e[id_b];
           const double gam = double(sg) * di * dj;
@@ -999,8 +1000,8 @@ __global__ __launch_bounds__(kJacobiThreads) void jacobi_reg_kernel(
           const T fb = T(td * di * ej);
           const T fa = T(td * dj * ei * cd * cd);
           if (active && lead && flag == 1) {
-            s_norm[id_t] = T(fma(-td, gam, al));
-            s_norm[id_b] = T(fma(td, gam, be));
+            s_norm[id_t] = fma(-td, gam, al);
+            s_norm[id_b] = fma(td, gam, be);
             s_d[id_t] = ic * di;
             s_d[id_b] = cd * dj;
             s_e[id_t] = cd * ei;
